@@ -1,0 +1,183 @@
+/*
+ * librp -- spin-coherent-state Monte Carlo singlet yields of radical pairs on MI355X.
+ *
+ * Method: A. M. Lewis, T. P. Fay, D. E. Manolopoulos, "An efficient quantum
+ * mechanical method for radical pair recombination reactions" (arXiv:1612.09517).
+ * The ensemble singlet yield Phi_S = k_S int P_S(t) dt (Eq. 20) is estimated by
+ * averaging single-wavepacket yields phi_S(Omega) (Eq. 22) over wavepackets
+ * |S> (x) |Omega_1> (x) ... (x) |Omega_N> whose nuclear spin coherent states
+ * (Eq. 15) point in directions sampled uniformly on each sphere (Eq. 18).
+ *
+ * Conventions shared by every entry point
+ *   - Units: hyperfine couplings, exchange and fields in mT (converted with
+ *     gamma to rad/us); rate constants k_S, k_T in 1/us; times in us.
+ *   - Hamiltonian (Eq. 1): H = omega (S1z + S2z) + sum_k a_k I_k.S_i(k) + 2 J S1.S2
+ *     with omega = gamma |B| along z (the yield is even in omega), no nuclear
+ *     Zeeman terms, hbar = 1.  Recombination by the Haberkorn operator
+ *     K = k_S/2 P_S + k_T/2 P_T (Eq. 2-4); wavepackets evolve by
+ *     exp(-iHt - Kt) (Eq. 13).
+ *   - Nuclei are listed radical 1 first, then radical 2.  Spin quantum numbers
+ *     are given as two_I = 2I (1 = spin-1/2, 2 = spin-1, ... at most 4).
+ *   - Device pointers are HIP device allocations on the current device; host
+ *     pointers are ordinary CPU memory.  The caller owns every buffer.
+ *   - All work is enqueued on the given HIP stream (NULL = default stream).
+ *     rp_sample and rp_yield return without waiting; rp_propagate waits for
+ *     its own work to finish before it returns (it checks a convergence
+ *     flag), so its outputs are ready on return.
+ *   - Errors: every entry point returns RP_OK (0) or a negative code.
+ *     Argument errors are detected before any device work is enqueued.
+ *     rp_last_error() gives a message for the most recent failure on the
+ *     calling thread.  The library never aborts the process.
+ */
+#ifndef RP_H
+#define RP_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  RP_OK = 0,
+  RP_EINVAL = -1,   /* bad sizes, null pointers, negative rates, T <= 0, spin or nucleus limits */
+  RP_ENOMEM = -2,   /* device workspace could not be allocated */
+  RP_EDEVICE = -3,  /* a HIP call failed */
+  RP_ENOTCONV = -4, /* wavepacket norm grew or became NaN: spectral bound violated */
+  RP_ENOTIMPL = -5  /* option not implemented */
+};
+
+#define RP_MAX_NUCLEI 40
+#define RP_MAX_TWO_I 4
+
+/* One radical pair (Sec. II).  Read only during a call; arrays are host memory. */
+typedef struct rp_system {
+  int32_t n_nuc[2];      /* N1, N2: nuclei on radical 1 and radical 2 (N1+N2 <= RP_MAX_NUCLEI) */
+  const int32_t *two_I;  /* [N1+N2] 2I per nucleus, 1..RP_MAX_TWO_I */
+  const double *a_mT;    /* [N1+N2] isotropic hyperfine constants a_ik/gamma in mT (Eq. 1) */
+  double J_mT;           /* exchange J/gamma in mT: term 2 J S1.S2 of Eq. 1 */
+  double kS, kT;         /* singlet and triplet recombination rate constants, 1/us, >= 0 (Eq. 2) */
+  double T_us;           /* upper limit of the yield integral (Eq. 20, 22 taken on [0, T]), > 0 */
+  double gamma;          /* electron gyromagnetic ratio in rad/us/mT; 0 selects 176.085963023 */
+} rp_system;
+
+/* Propagation options.  Zero-initialised options select the defaults. */
+typedef struct rp_opts {
+  int32_t precision;        /* 64: complex FP64 wavepackets; 32: complex FP32 wavepackets with FP64
+                               coefficients, bounds and yield accumulation.  0 selects 64. */
+  int32_t init_mode;        /* 0: angles hold (cos theta, phi) per nucleus: coherent states (Eq. 15);
+                               1: angles[..][0] holds the digit n = I - m per nucleus: the basis
+                               state |S, M_1, M_2> of Eq. 12 (the [..][1] entry is ignored). */
+  double tol;               /* Chebyshev truncation tolerance; 0 selects 1e-14 (64) or 1e-9 (32) */
+  double rdt;               /* target r*dt of one Chebyshev step (r = spectral half-width); 0 = 80 */
+  double r_scale;           /* multiplies the spectral half-width bound; 0 selects 1.  Values below 1
+                               under-estimate the spectrum and exist to test RP_ENOTCONV. */
+  int64_t workspace_bytes;  /* cap on device workspace per call; 0 selects half of free memory */
+  int32_t flags;            /* bit mask of RP_FLAG_* */
+  int32_t reserved;         /* must be 0 */
+} rp_opts;
+
+/* opts->flags: record HIP events around the Chebyshev-term launches of every step
+   and keep the totals for rp_profile_last (adds a few event records per step). */
+#define RP_FLAG_PROFILE 1
+
+/*
+ * rp_sample -- directions of the nuclear coherent states (Eq. 18: uniform on
+ * each sphere, measure dOmega / 4 pi), or basis-state digits.
+ *
+ *   s            system (only N1+N2 and two_I are read)
+ *   seed, stream_id  Philox4x64-10 key (seed, stream_id); stream ids separate
+ *                uses (0 evaluation, 1 training, 2 quadrature, 3 spare)
+ *   first_sample global index of the first sample (counter word 0)
+ *   M            number of samples, >= 0
+ *   basis_mode   0: coherent-state directions (cos theta, phi), with
+ *                   cos theta = 2 u1 - 1, phi = 2 pi u2, u = (floor(w/2^12) + 1/2) 2^-52
+ *                   from words 0 and 1 of Philox(counter = (sample, nucleus, 0, 0));
+ *                1: random basis states, digit n = floor(u1 (2I+1)) (Sec. V, last
+ *                   paragraph: sampling of J_z eigenstates);
+ *                2: deterministic enumeration, sample s -> digits of s in the mixed
+ *                   radix of the nuclei (first nucleus fastest), for the Eq. 14 sum.
+ *   angles       device, [M][N1+N2][2] doubles, written.
+ */
+int rp_sample(const rp_system *s, uint64_t seed, uint32_t stream_id, uint64_t first_sample,
+              int64_t M, int32_t basis_mode, double *angles, void *hip_stream);
+
+/*
+ * rp_propagate -- single-wavepacket singlet yields phi_S (Eq. 22 on [0, T]) for
+ * every system, field and sample.
+ *
+ *   sys        [n_sys] systems
+ *   B_mT       host, [n_sys][nB] field strengths in mT
+ *   angles     device, the concatenation over systems of [M][N_i][2] arrays as
+ *              written by rp_sample (interpretation set by opts->init_mode)
+ *   M          samples per system
+ *   opts       options (NULL = defaults)
+ *   phi        device, [n_sys][nB][M] doubles, written
+ *   ps_t       must be NULL (trajectory output is not implemented: RP_ENOTIMPL)
+ *
+ * Each wavepacket is propagated by a Chebyshev expansion of exp(-iGt),
+ * G = H - iK, in steps of length dt; the time integral of P_S within each step
+ * is exact up to the truncation tolerance (Gauss-Legendre integrals of products
+ * of Bessel functions, factored by pivoted Cholesky).
+ */
+int rp_propagate(const rp_system *sys, int32_t n_sys, const double *B_mT, int32_t nB,
+                 const double *angles, int64_t M, const rp_opts *opts, double *phi, double *ps_t,
+                 void *hip_stream);
+
+/*
+ * rp_yield -- per-field Monte Carlo mean and standard error (Eq. 18, Eq. 23:
+ * eps = s / sqrt(M), s with the 1/(M-1) normalisation).
+ *
+ *   phi       device, [nB][M] single-wavepacket yields
+ *   cv_g      device [nB][M] control-variate values g, or NULL for the plain mean
+ *   cv_mu     device [nB] known means of g (ignored when cv_g is NULL)
+ *   cv_beta   device [nB] coefficients (ignored when cv_g is NULL); the estimate is
+ *             mean(phi - beta (g - mu)), unbiased when mu = E[g] and beta is fixed
+ *   mean, stderr_  device [nB] outputs
+ */
+int rp_yield(const double *phi, int32_t nB, int64_t M, const double *cv_g, const double *cv_mu,
+             const double *cv_beta, double *mean, double *stderr_, void *hip_stream);
+
+/*
+ * rp_profile_last -- timing of the most recent rp_propagate call on the calling
+ * thread that had RP_FLAG_PROFILE set.  out (host, n <= 8 doubles):
+ *   [0] milliseconds spent in Chebyshev-term kernels (events on the call's stream)
+ *   [1] number of Chebyshev-term kernel launches
+ *   [2] wavepacket elements processed by them (sum over launches of jobs * 4Z)
+ *   [3] algorithmic bytes per element and term: read phi_n, phi_{n-1} and the step
+ *       accumulator, write phi_{n+1} and the accumulator (5 complex numbers) plus the
+ *       singlet amplitude (1/4 complex per element): 42 (complex FP32) or 84 (FP64)
+ *   [4] milliseconds in the in-step quadrature kernels, [5] their launches
+ *   [6] milliseconds of the whole call, [7] Chebyshev terms per step (padded maximum)
+ * Returns the number of values written.
+ */
+int rp_profile_last(double *out, int32_t n);
+
+/* Static text for a return code. */
+const char *rp_strerror(int code);
+
+/* Message for the most recent failure on the calling thread ("" if none). */
+const char *rp_last_error(void);
+
+/*
+ * Host-only planning helpers (no device work; used to test the propagator's
+ * coefficients on a machine without a GPU).
+ *
+ * rp_bessel_j: J_0(x) .. J_nmax(x) for x >= 0 by Miller's backward recurrence
+ *   normalised with J_0 + 2 sum_k J_2k = 1.  out: host [nmax+1].
+ *
+ * rp_plan_field: the Chebyshev step plan for one system at one field.
+ *   info (host, 8 doubles): r, c_re, c_im, dt, n_steps, n_terms (N+1), rank R, x = r dt
+ *   coef (host or NULL, 2*n_terms doubles): complex a_n of one step, interleaved re/im
+ *   ell  (host or NULL, n_terms*R doubles): real factor of the in-step quadrature,
+ *        row n, column r, including the (2 - delta_n0) and 1/sqrt(2) factors
+ */
+int rp_bessel_j(double x, int32_t nmax, double *out);
+int rp_plan_field(const rp_system *s, double B_mT, const rp_opts *opts, double *info, double *coef,
+                  double *ell);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RP_H */

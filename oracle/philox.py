@@ -60,3 +60,30 @@ def flip(angles, mask):
     a[mask, 0] = -a[mask, 0]
     a[mask, 1] = np.mod(a[mask, 1] + math.pi, TWO_PI)
     return a
+
+
+def sample_basis_digits(seed, first_sample, M, two_I, stream=STREAM_EVAL):
+    """Random J_z eigenstates (Sec. V, last paragraph): digit n_k = floor(u1 (2I_k + 1)),
+    u1 from word 0 of the same Philox block as the coherent-state sampler."""
+    N = len(two_I)
+    out = np.zeros((M, N, 2), float)
+    for s in range(M):
+        for k in range(N):
+            w = philox4x64((first_sample + s, k, 0, 0), (seed, stream))
+            d = two_I[k] + 1
+            out[s, k, 0] = min(int(word_to_unit(w[0]) * d), d - 1)
+    return out
+
+
+def enumerate_basis_digits(first_sample, M, two_I):
+    """Deterministic enumeration of the basis of Eq. 12: sample s -> mixed-radix digits of s
+    (first nucleus fastest), so samples 0..Z-1 visit every |M_1, M_2> once (Eq. 14)."""
+    N = len(two_I)
+    out = np.zeros((M, N, 2), float)
+    for s in range(M):
+        q = first_sample + s
+        for k in range(N):
+            d = two_I[k] + 1
+            out[s, k, 0] = q % d
+            q //= d
+    return out

@@ -1,0 +1,95 @@
+// Device-side data structures and kernels of librp (gfx950, wave64).
+//
+// Wavepacket layout in HBM: one job (system, field, sample) owns a contiguous
+// vector of 4Z complex numbers, element index  e + 4 M,  where e = 2 b1 + b2
+// enumerates the electron product states (aa, ab, ba, bb) with b = 1 for beta,
+// and M = sum_k n_k stride_k is the mixed-radix nuclear index with digit
+// n_k = I_k - m_k (first nucleus fastest).  Interleaved (re, im).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "rp.h"
+
+namespace rp {
+
+constexpr int kBlock = 256;   // threads per workgroup: one nuclear index M per thread
+constexpr int kQuadChunk = 16;
+
+template <typename R>
+struct cx {
+  R x, y;
+};
+
+// Per-system constants in the kernel-argument segment (uniform across the grid).
+template <typename R>
+struct SysArgs {
+  int32_t N, N1, all_half, pad;
+  int64_t Z;
+  R J;       // exchange (rad/us): diagonal +-J/2, ab<->ba coupling J
+  R beta;    // coefficient of i*beta*P_S in the kernel operator
+  int32_t stride[RP_MAX_NUCLEI];
+  int32_t d[RP_MAX_NUCLEI];
+  int32_t shift[RP_MAX_NUCLEI];        // log2(stride) for all-spin-1/2 systems
+  R a[RP_MAX_NUCLEI];                  // a_k (rad/us), for the diagonal sum a_k m_k
+  R f[RP_MAX_NUCLEI][RP_MAX_TWO_I];    // (a_k/2) sqrt(I(I+1) - m(m-1)), link between digits n, n+1
+};
+
+// Per-field constants of one Chebyshev step.
+template <typename R>
+struct FieldDev {
+  R omega;        // gamma |B|
+  R c_re, c_im;   // shift of the kernel operator (includes -i dk/2 when P_T is dissipative)
+  R s1, s2;       // 1/r and 2/r
+};
+
+template <typename R>
+struct TermArgs {
+  const cx<R> *phin;       // phi_n, [jobs][4Z]
+  cx<R> *phio;             // in: phi_{n-1}; out: phi_{n+1} (same storage)
+  cx<R> *acc;              // running sum_n a_n phi_n
+  cx<R> *dnext;            // singlet amplitudes of phi_{n+1}: [jobs][Z]
+  cx<R> *dfirst;           // first term only: singlet amplitudes of phi_0
+  const FieldDev<R> *fields;
+  const cx<R> *coef;       // [fields][n_terms]
+  const int32_t *job_field;
+  double *part_norm;       // first term only: [jobs][nbx]
+  int64_t nbx;
+  int32_t njobs;
+  int32_t n;               // producing phi_{n+1}
+  int32_t n_terms;
+  int32_t pad;
+};
+
+template <typename R>
+struct QuadArgs {
+  const cx<R> *d;          // [n_terms][slab]
+  int64_t slab;            // elements per term slab (jobs_in_chunk * Z)
+  const R *ell;            // [fields][n_terms][rank_pad]
+  const int32_t *job_field;
+  double *part;            // [jobs][nbx][2]: quadratic form, |d_0|^2/2
+  int64_t Z;
+  int64_t nbx;
+  int32_t njobs;
+  int32_t n_terms;
+  int32_t rank_pad;
+  int32_t pad;
+};
+
+struct FinArgs {
+  const double *part_q;    // [jobs][nbx][2]
+  const double *part_norm; // [jobs][nbx]
+  double *phi;             // [jobs] accumulated yields of this chunk
+  double *prev_norm;       // [jobs]
+  int *flag;
+  const int32_t *job_field;
+  const double *dt;        // [fields]
+  int64_t nbx;
+  int32_t njobs;
+  int32_t step;
+  double kS, kmin, rtol;
+};
+
+}  // namespace rp

@@ -1,0 +1,1020 @@
+// librp: HIP kernels for gfx950 and the C-ABI entry points declared in include/rp.h.
+//
+// Hot loop: one launch per Chebyshev term applies the matrix-free generator
+//   Gh x = ((H + i beta P_S - c) x) / r
+// of Eq. 1-4 to every active wavepacket of a chunk, with
+//   H x  (e, M) = diag(e, M) x(e, M) + J x(e^3, M)[e = ab, ba]
+//                + sum_k f_k x(e ^ flip_i(k), M +- stride_k)       (flip-flop terms a_k/2 (I+ S- + I- S+)),
+// writes phi_{n+1} = 2 Gh phi_n - phi_{n-1} over phi_{n-1}, the singlet amplitude
+// <S|phi_{n+1}(M)> (times sqrt 2) into a per-term slab, and adds a_{n+1} phi_{n+1}
+// to the accumulator of the step.  At the end of each step one launch contracts
+// the per-term slabs with the in-step quadrature factor (the exact time integral
+// of P_S over the step), and one launch adds the weighted result to phi_S.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <numeric>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "kernels.hpp"
+#include "plan.hpp"
+#include "rp.h"
+
+namespace rp {
+
+// ----------------------------------------------------------------------------- complex helpers
+template <typename R>
+__device__ __forceinline__ cx<R> cadd(cx<R> a, cx<R> b) { return {a.x + b.x, a.y + b.y}; }
+template <typename R>
+__device__ __forceinline__ cx<R> csub(cx<R> a, cx<R> b) { return {a.x - b.x, a.y - b.y}; }
+template <typename R>
+__device__ __forceinline__ cx<R> cscale(R s, cx<R> a) { return {s * a.x, s * a.y}; }
+template <typename R>
+__device__ __forceinline__ cx<R> cmul(cx<R> a, cx<R> b) { return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x}; }
+template <typename R>
+__device__ __forceinline__ cx<R> csel(bool c, cx<R> a, cx<R> b) { return {c ? a.x : b.x, c ? a.y : b.y}; }
+
+// Workgroup b of a 1-D grid runs on XCD b % 8.  Give each XCD a contiguous range
+// of logical blocks so that all blocks of one wavepacket share that XCD's L2.
+__device__ __forceinline__ int64_t xcd_remap(int64_t b, int64_t total) {
+  const int64_t q = total >> 3, rem = total & 7;
+  const int64_t x = b & 7, slot = b >> 3;
+  return x * q + (x < rem ? x : rem) + slot;
+}
+
+__device__ __forceinline__ double warp_sum(double v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// Sum over the 256 threads of a workgroup (every thread must call it).
+__device__ __forceinline__ double block_sum(double v, double *lds) {
+  v = warp_sum(v);
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) lds[w] = v;
+  __syncthreads();
+  double t = 0.0;
+  if (threadIdx.x == 0) t = lds[0] + lds[1] + lds[2] + lds[3];
+  __syncthreads();
+  return t;
+}
+
+// ----------------------------------------------------------------------------- sampler (Eq. 18)
+struct SampleArgs {
+  double *angles;
+  uint64_t seed, first;
+  int64_t M;
+  int32_t N, mode;
+  uint32_t stream;
+  int32_t d[RP_MAX_NUCLEI];
+  int64_t radix[RP_MAX_NUCLEI];
+};
+
+__device__ __forceinline__ void philox4x64_10(uint64_t c[4], uint64_t k0, uint64_t k1) {
+  const uint64_t M0 = 0xD2E7470EE14C6C93ull, M1 = 0xCA5A826395121157ull;
+  const uint64_t W0 = 0x9E3779B97F4A7C15ull, W1 = 0xBB67AE8584CAA73Bull;
+  for (int r = 0; r < 10; ++r) {
+    if (r) {
+      k0 += W0;
+      k1 += W1;
+    }
+    const uint64_t hi0 = __umul64hi(M0, c[0]), lo0 = M0 * c[0];
+    const uint64_t hi1 = __umul64hi(M1, c[2]), lo1 = M1 * c[2];
+    const uint64_t n0 = hi1 ^ c[1] ^ k0, n2 = hi0 ^ c[3] ^ k1;
+    c[0] = n0;
+    c[1] = lo1;
+    c[2] = n2;
+    c[3] = lo0;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_sample(SampleArgs a) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= a.M * a.N) return;
+  const int64_t s = i / a.N;
+  const int k = (int)(i - s * a.N);
+  uint64_t c[4] = {a.first + (uint64_t)s, (uint64_t)k, 0ull, 0ull};
+  philox4x64_10(c, a.seed, (uint64_t)a.stream);
+  const double u1 = ((double)(c[0] >> 12) + 0.5) * 0x1p-52;
+  const double u2 = ((double)(c[1] >> 12) + 0.5) * 0x1p-52;
+  double v0, v1 = 0.0;
+  if (a.mode == 0) {
+    v0 = 2.0 * u1 - 1.0;
+    v1 = 6.283185307179586 * u2;
+  } else if (a.mode == 1) {
+    int dg = (int)(u1 * (double)a.d[k]);
+    v0 = (double)(dg < a.d[k] ? dg : a.d[k] - 1);
+  } else {
+    v0 = (double)(((a.first + (uint64_t)s) / (uint64_t)a.radix[k]) % (uint64_t)a.d[k]);
+  }
+  a.angles[2 * i] = v0;
+  a.angles[2 * i + 1] = v1;
+}
+
+// ----------------------------------------------------------------------------- initial wavepacket
+struct CohArgs {
+  const double *angles;   // [M][N][2]
+  cx<double> *tab;        // [M][N][RP_MAX_TWO_I+1]
+  int64_t M;
+  int32_t N, mode;
+  int32_t two_I[RP_MAX_NUCLEI];
+};
+
+// Components <I, I-n | Omega> of the coherent state of Eq. 15:
+//   sqrt(C(2I, n)) (cos theta/2)^(2I-n) (sin theta/2)^n exp(i n phi),
+// which is the power series of exp(tan(theta/2) e^{i phi} J_-) |I,I> times (cos theta/2)^{2I}.
+__global__ __launch_bounds__(256) void k_coherent(CohArgs a) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= a.M * a.N) return;
+  const int k = (int)(i % a.N);
+  const int t = a.two_I[k];
+  cx<double> *out = a.tab + i * (RP_MAX_TWO_I + 1);
+  const double v0 = a.angles[2 * i], v1 = a.angles[2 * i + 1];
+  if (a.mode == 1) {
+    const int dg = (int)v0;
+    for (int n = 0; n <= RP_MAX_TWO_I; ++n) out[n] = {n == dg ? 1.0 : 0.0, 0.0};
+    return;
+  }
+  const double ch = sqrt(fmax(0.0, 0.5 * (1.0 + v0)));
+  const double sh = sqrt(fmax(0.0, 0.5 * (1.0 - v0)));
+  // sqrt of binomial coefficients C(t, n) for t <= 4
+  const double sb[5][5] = {{1, 0, 0, 0, 0},
+                           {1, 1, 0, 0, 0},
+                           {1, 1.4142135623730951, 1, 0, 0},
+                           {1, 1.7320508075688772, 1.7320508075688772, 1, 0},
+                           {1, 2, 2.449489742783178, 2, 1}};
+  for (int n = 0; n <= RP_MAX_TWO_I; ++n) {
+    if (n > t) {
+      out[n] = {0.0, 0.0};
+      continue;
+    }
+    double mag = sb[t][n];
+    for (int q = 0; q < t - n; ++q) mag *= ch;
+    for (int q = 0; q < n; ++q) mag *= sh;
+    double sn, cs;
+    sincos((double)n * v1, &sn, &cs);
+    out[n] = {mag * cs, mag * sn};
+  }
+}
+
+template <typename R>
+struct InitArgs {
+  cx<R> *psi;                   // [jobs][4Z]
+  const cx<double> *tab;        // [M][N][5]
+  const int32_t *job_sample;    // [jobs]
+  int64_t Z;
+  int64_t nbx;
+  int32_t njobs, N;
+  int32_t stride[RP_MAX_NUCLEI];
+  int32_t d[RP_MAX_NUCLEI];
+};
+
+// psi_0 = |S> (x) prod_k |Omega_k>, |S> = (|ab> - |ba>)/sqrt 2 (Eq. 10, 18-19).
+template <typename R>
+__global__ __launch_bounds__(256) void k_init(InitArgs<R> a) {
+  const int64_t total = (int64_t)a.njobs * a.nbx;
+  const int64_t L = xcd_remap(blockIdx.x, total);
+  const int64_t job = L / a.nbx, bx = L - job * a.nbx;
+  const int64_t M = bx * kBlock + threadIdx.x;
+  if (M >= a.Z) return;
+  const cx<double> *t = a.tab + (int64_t)a.job_sample[job] * a.N * (RP_MAX_TWO_I + 1);
+  cx<double> p = {M_SQRT1_2, 0.0};
+  for (int k = 0; k < a.N; ++k) {
+    const int n = (int)((M / a.stride[k]) % a.d[k]);
+    const cx<double> c = t[k * (RP_MAX_TWO_I + 1) + n];
+    p = {p.x * c.x - p.y * c.y, p.x * c.y + p.y * c.x};
+  }
+  cx<R> *o = a.psi + (job * a.Z + M) * 4;
+  o[0] = {R(0), R(0)};
+  o[1] = {R(p.x), R(p.y)};
+  o[2] = {R(-p.x), R(-p.y)};
+  o[3] = {R(0), R(0)};
+}
+
+// ----------------------------------------------------------------------------- Chebyshev term
+template <typename R>
+__device__ __forceinline__ void load2(const cx<R> *p, cx<R> &a, cx<R> &b) {
+  a = p[0];
+  b = p[1];
+}
+template <>
+__device__ __forceinline__ void load2<float>(const cx<float> *p, cx<float> &a, cx<float> &b) {
+  const float4 v = *reinterpret_cast<const float4 *>(p);
+  a = {v.x, v.y};
+  b = {v.z, v.w};
+}
+
+template <typename R, bool HALF, bool FIRST>
+__global__ __launch_bounds__(256) void k_cheb(TermArgs<R> ta, SysArgs<R> sa) {
+  __shared__ double lds[4];
+  const int64_t total = (int64_t)ta.njobs * ta.nbx;
+  const int64_t L = xcd_remap(blockIdx.x, total);
+  const int64_t job = L / ta.nbx, bx = L - job * ta.nbx;
+  const int64_t M = bx * kBlock + threadIdx.x;
+  const bool live = M < sa.Z;
+  const int fi = ta.job_field[job];
+  const FieldDev<R> fp = ta.fields[fi];
+  double nrm = 0.0;
+  if (live) {
+    const cx<R> *X = ta.phin + job * sa.Z * 4;
+    cx<R> x0, x1, x2, x3;
+    load2(X + 4 * M, x0, x1);
+    load2(X + 4 * M + 2, x2, x3);
+    cx<R> y0 = {R(0), R(0)}, y1 = y0, y2 = y0, y3 = y0;
+    R h1 = R(0), h2 = R(0);
+    for (int k = 0; k < sa.N; ++k) {
+      if (HALF) {
+        const int bit = (int)((M >> sa.shift[k]) & 1);
+        const int64_t P = M ^ (int64_t)sa.stride[k];
+        const R fk = sa.f[k][0];
+        const R mk = bit ? R(-0.5) : R(0.5);
+        if (k < sa.N1) {
+          h1 += sa.a[k] * mk;
+          cx<R> p0, p1;
+          load2(X + 4 * P + 2 * bit, p0, p1);   // bit 0: (aa, ab) -> (ba, bb); bit 1: (ba, bb) -> (aa, ab)
+          const cx<R> u0 = cscale(fk, p0), u1 = cscale(fk, p1);
+          y0 = cadd(y0, csel(bit, u0, cx<R>{R(0), R(0)}));
+          y1 = cadd(y1, csel(bit, u1, cx<R>{R(0), R(0)}));
+          y2 = cadd(y2, csel(bit, cx<R>{R(0), R(0)}, u0));
+          y3 = cadd(y3, csel(bit, cx<R>{R(0), R(0)}, u1));
+        } else {
+          h2 += sa.a[k] * mk;
+          const cx<R> p0 = X[4 * P + bit], p1 = X[4 * P + bit + 2];  // bit 0: (aa, ba); bit 1: (ab, bb)
+          const cx<R> u0 = cscale(fk, p0), u1 = cscale(fk, p1);
+          y0 = cadd(y0, csel(bit, u0, cx<R>{R(0), R(0)}));
+          y2 = cadd(y2, csel(bit, u1, cx<R>{R(0), R(0)}));
+          y1 = cadd(y1, csel(bit, cx<R>{R(0), R(0)}, u0));
+          y3 = cadd(y3, csel(bit, cx<R>{R(0), R(0)}, u1));
+        }
+      } else {
+        const int64_t st = sa.stride[k];
+        const int dk = sa.d[k];
+        const int n = (int)((M / st) % dk);
+        const R mk = R(0.5) * R(dk - 1) - R(n);
+        const bool r1 = k < sa.N1;
+        if (r1) h1 += sa.a[k] * mk; else h2 += sa.a[k] * mk;
+        if (n > 0) {        // partner digit n-1: beta component -> alpha component (I- S+)
+          const R fk = sa.f[k][n - 1];
+          const cx<R> *Pp = X + 4 * (M - st);
+          if (r1) {
+            y0 = cadd(y0, cscale(fk, Pp[2]));
+            y1 = cadd(y1, cscale(fk, Pp[3]));
+          } else {
+            y0 = cadd(y0, cscale(fk, Pp[1]));
+            y2 = cadd(y2, cscale(fk, Pp[3]));
+          }
+        }
+        if (n < dk - 1) {   // partner digit n+1: alpha component -> beta component (I+ S-)
+          const R fk = sa.f[k][n];
+          const cx<R> *Pp = X + 4 * (M + st);
+          if (r1) {
+            y2 = cadd(y2, cscale(fk, Pp[0]));
+            y3 = cadd(y3, cscale(fk, Pp[1]));
+          } else {
+            y1 = cadd(y1, cscale(fk, Pp[0]));
+            y3 = cadd(y3, cscale(fk, Pp[2]));
+          }
+        }
+      }
+    }
+    // Diagonal: omega (s1 + s2) + s1 h1 + s2 h2 + 2 J s1 s2 with s = +-1/2.
+    const R hs = R(0.5) * (h1 + h2), hd = R(0.5) * (h1 - h2), hj = R(0.5) * sa.J;
+    y0 = cadd(y0, cscale(fp.omega + hs + hj, x0));
+    y1 = cadd(y1, cadd(cscale(hd - hj, x1), cscale(sa.J, x2)));
+    y2 = cadd(y2, cadd(cscale(-hd - hj, x2), cscale(sa.J, x1)));
+    y3 = cadd(y3, cscale(-fp.omega - hs + hj, x3));
+    // i beta P_S x: P_S acts on (ab, ba) as [[1,-1],[-1,1]]/2.
+    const cx<R> t = {R(0.5) * (x1.x - x2.x), R(0.5) * (x1.y - x2.y)};
+    const cx<R> ibt = {-sa.beta * t.y, sa.beta * t.x};
+    y1 = cadd(y1, ibt);
+    y2 = csub(y2, ibt);
+    // (y - c x) / r, doubled for the three-term recurrence.
+    const cx<R> c = {fp.c_re, fp.c_im};
+    const R s = FIRST ? fp.s1 : fp.s2;
+    cx<R> z0 = cscale(s, csub(y0, cmul(c, x0)));
+    cx<R> z1 = cscale(s, csub(y1, cmul(c, x1)));
+    cx<R> z2 = cscale(s, csub(y2, cmul(c, x2)));
+    cx<R> z3 = cscale(s, csub(y3, cmul(c, x3)));
+    cx<R> *O = ta.phio + (job * sa.Z + M) * 4;
+    if (!FIRST) {
+      cx<R> o0, o1, o2, o3;
+      load2(O, o0, o1);
+      load2(O + 2, o2, o3);
+      z0 = csub(z0, o0);
+      z1 = csub(z1, o1);
+      z2 = csub(z2, o2);
+      z3 = csub(z3, o3);
+    }
+    O[0] = z0;
+    O[1] = z1;
+    O[2] = z2;
+    O[3] = z3;
+    ta.dnext[job * sa.Z + M] = csub(z1, z2);
+    const cx<R> an = ta.coef[(int64_t)fi * ta.n_terms + ta.n + 1];
+    cx<R> *A = ta.acc + (job * sa.Z + M) * 4;
+    if (FIRST) {
+      const cx<R> a0 = ta.coef[(int64_t)fi * ta.n_terms];
+      A[0] = cadd(cmul(a0, x0), cmul(an, z0));
+      A[1] = cadd(cmul(a0, x1), cmul(an, z1));
+      A[2] = cadd(cmul(a0, x2), cmul(an, z2));
+      A[3] = cadd(cmul(a0, x3), cmul(an, z3));
+      ta.dfirst[job * sa.Z + M] = csub(x1, x2);
+      nrm = (double)x0.x * x0.x + (double)x0.y * x0.y + (double)x1.x * x1.x + (double)x1.y * x1.y +
+            (double)x2.x * x2.x + (double)x2.y * x2.y + (double)x3.x * x3.x + (double)x3.y * x3.y;
+    } else {
+      cx<R> a0v, a1v, a2v, a3v;
+      load2(A, a0v, a1v);
+      load2(A + 2, a2v, a3v);
+      A[0] = cadd(a0v, cmul(an, z0));
+      A[1] = cadd(a1v, cmul(an, z1));
+      A[2] = cadd(a2v, cmul(an, z2));
+      A[3] = cadd(a3v, cmul(an, z3));
+    }
+  }
+  if (FIRST) {
+    const double t = block_sum(nrm, lds);
+    if (threadIdx.x == 0) ta.part_norm[job * ta.nbx + bx] = t;
+  }
+}
+
+// ----------------------------------------------------------------------------- in-step quadrature
+// part[job][bx] = ( sum_M sum_r |sum_n ell_nr (-i)^n d_n(M)|^2 ,  sum_M |d_0(M)|^2 / 2 )
+template <typename R>
+__global__ __launch_bounds__(256) void k_quad(QuadArgs<R> qa) {
+  __shared__ double lds[4];
+  const int64_t total = (int64_t)qa.njobs * qa.nbx;
+  const int64_t L = xcd_remap(blockIdx.x, total);
+  const int64_t job = L / qa.nbx, bx = L - job * qa.nbx;
+  const int64_t M = bx * kBlock + threadIdx.x;
+  const bool live = M < qa.Z;
+  const int fi = qa.job_field[job];
+  const R *ell = qa.ell + (int64_t)fi * qa.n_terms * qa.rank_pad;
+  double acc = 0.0, ps = 0.0;
+  if (live) {
+    const cx<R> *dp = qa.d + job * qa.Z + M;
+    for (int r0 = 0; r0 < qa.rank_pad; r0 += kQuadChunk) {
+      cx<R> W[kQuadChunk];
+#pragma unroll
+      for (int r = 0; r < kQuadChunk; ++r) W[r] = {R(0), R(0)};
+      for (int n = 0; n < qa.n_terms; ++n) {
+        const cx<R> v = dp[(int64_t)n * qa.slab];
+        cx<R> u;
+        switch (n & 3) {          // multiply by (-i)^n
+          case 0: u = v; break;
+          case 1: u = {v.y, -v.x}; break;
+          case 2: u = {-v.x, -v.y}; break;
+          default: u = {-v.y, v.x}; break;
+        }
+        const R *e = ell + (int64_t)n * qa.rank_pad + r0;
+#pragma unroll
+        for (int r = 0; r < kQuadChunk; ++r) {
+          W[r].x += e[r] * u.x;
+          W[r].y += e[r] * u.y;
+        }
+      }
+#pragma unroll
+      for (int r = 0; r < kQuadChunk; ++r) acc += (double)W[r].x * W[r].x + (double)W[r].y * W[r].y;
+    }
+    const cx<R> v0 = dp[0];
+    ps = 0.5 * ((double)v0.x * v0.x + (double)v0.y * v0.y);
+  }
+  const double s0 = block_sum(acc, lds);
+  const double s1 = block_sum(ps, lds);
+  if (threadIdx.x == 0) {
+    qa.part[(job * qa.nbx + bx) * 2] = s0;
+    qa.part[(job * qa.nbx + bx) * 2 + 1] = s1;
+  }
+}
+
+// ----------------------------------------------------------------------------- per-step finalisation
+__global__ __launch_bounds__(256) void k_finalize(FinArgs fa) {
+  const int64_t job = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (job >= fa.njobs) return;
+  double y = 0.0, nrm = 0.0;
+  for (int64_t b = 0; b < fa.nbx; ++b) {
+    y += fa.part_q[(job * fa.nbx + b) * 2];
+    nrm += fa.part_norm[job * fa.nbx + b];
+  }
+  const int fi = fa.job_field[job];
+  const double decay = exp(-fa.kmin * fa.step * fa.dt[fi]);
+  fa.phi[job] += fa.kS * decay * y;
+  const double Nt = decay * nrm;           // population N(t_j) of the wavepacket
+  if (!(Nt <= fa.prev_norm[job] * (1.0 + fa.rtol) + 1e-300) || !(y == y)) atomicOr(fa.flag, 1);
+  fa.prev_norm[job] = Nt;
+}
+
+__global__ __launch_bounds__(256) void k_fill(double *p, int64_t n, double v) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+__global__ __launch_bounds__(256) void k_scatter(const double *src, const int64_t *dst_idx, double *dst,
+                                                 int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) dst[dst_idx[i]] = src[i];
+}
+
+// ----------------------------------------------------------------------------- statistics (Eq. 23)
+struct StatArgs {
+  const double *phi, *g, *mu, *beta;
+  double *mean, *err;
+  int64_t M;
+};
+
+__global__ __launch_bounds__(256) void k_stats(StatArgs a) {
+  __shared__ double lds[4];
+  const int b = blockIdx.x;
+  const double *p = a.phi + (int64_t)b * a.M;
+  const double *g = a.g ? a.g + (int64_t)b * a.M : nullptr;
+  const double be = a.g ? a.beta[b] : 0.0, mu = a.g ? a.mu[b] : 0.0;
+  double s = 0.0;
+  for (int64_t i = threadIdx.x; i < a.M; i += blockDim.x) s += g ? p[i] - be * (g[i] - mu) : p[i];
+  const double tot = block_sum(s, lds);
+  __shared__ double mean_s;
+  if (threadIdx.x == 0) mean_s = tot / (double)a.M;
+  __syncthreads();
+  const double m = mean_s;
+  double q = 0.0;
+  for (int64_t i = threadIdx.x; i < a.M; i += blockDim.x) {
+    const double v = (g ? p[i] - be * (g[i] - mu) : p[i]) - m;
+    q += v * v;
+  }
+  const double qt = block_sum(q, lds);
+  if (threadIdx.x == 0) {
+    a.mean[b] = m;
+    a.err[b] = a.M > 1 ? sqrt(qt / (double)(a.M - 1) / (double)a.M) : 0.0;
+  }
+}
+
+// ============================================================================= host side
+static thread_local std::string g_err;
+
+static int fail(int code, const std::string &m) {
+  g_err = m;
+  return code;
+}
+
+#define HIPCHK(call)                                                                   \
+  do {                                                                                 \
+    hipError_t e_ = (call);                                                            \
+    if (e_ != hipSuccess) return fail(RP_EDEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+static int validate_system(const rp_system *s) {
+  if (!s) return fail(RP_EINVAL, "null system");
+  const int N1 = s->n_nuc[0], N2 = s->n_nuc[1];
+  if (N1 < 0 || N2 < 0 || N1 + N2 > RP_MAX_NUCLEI) return fail(RP_EINVAL, "nucleus counts out of range");
+  if (N1 + N2 > 0 && (!s->two_I || !s->a_mT)) return fail(RP_EINVAL, "null two_I or a_mT");
+  double Z = 1.0;
+  for (int k = 0; k < N1 + N2; ++k) {
+    if (s->two_I[k] < 1 || s->two_I[k] > RP_MAX_TWO_I) return fail(RP_EINVAL, "two_I out of range 1..4");
+    if (!std::isfinite(s->a_mT[k])) return fail(RP_EINVAL, "non-finite hyperfine constant");
+    Z *= s->two_I[k] + 1;
+  }
+  if (Z > 2147483647.0 / 4) return fail(RP_EINVAL, "nuclear Hilbert space too large");
+  if (!(s->kS >= 0.0) || !(s->kT >= 0.0) || !std::isfinite(s->kS) || !std::isfinite(s->kT))
+    return fail(RP_EINVAL, "rate constants must be finite and >= 0");
+  if (!(s->T_us > 0.0) || !std::isfinite(s->T_us)) return fail(RP_EINVAL, "T must be > 0");
+  if (!std::isfinite(s->J_mT)) return fail(RP_EINVAL, "non-finite J");
+  if (s->gamma < 0.0 || !std::isfinite(s->gamma)) return fail(RP_EINVAL, "gamma must be >= 0");
+  return RP_OK;
+}
+
+struct Profile {
+  double term_ms = 0, term_launches = 0, elems = 0, bytes_per_elem = 0, quad_ms = 0, quad_launches = 0,
+         total_ms = 0, terms = 0;
+};
+static thread_local Profile g_prof;
+
+// Event pairs around groups of launches, resolved after the stream is synchronised.
+struct EventLog {
+  bool on = false;
+  std::vector<hipEvent_t> ev;
+  std::vector<int> kind;   // 0: term kernels, 1: quadrature
+  hipEvent_t mark(hipStream_t st) {
+    hipEvent_t e = nullptr;
+    if (!on) return e;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    (void)hipEventRecord(e, st);
+    ev.push_back(e);
+    return e;
+  }
+  void close(int k) { if (on) kind.push_back(k); }
+  void resolve(Profile &p) {
+    for (size_t i = 0; i + 1 < ev.size(); i += 2) {
+      float ms = 0.f;
+      if (ev[i] && ev[i + 1] && hipEventElapsedTime(&ms, ev[i], ev[i + 1]) == hipSuccess) {
+        if (kind[i / 2] == 0) p.term_ms += ms; else p.quad_ms += ms;
+      }
+    }
+  }
+  ~EventLog() { for (auto e : ev) if (e) (void)hipEventDestroy(e); }
+};
+
+static double gamma_of(const rp_system *s) { return s->gamma > 0.0 ? s->gamma : 176.085963023; }
+
+struct Opts {
+  int precision = 64, init_mode = 0, flags = 0;
+  double tol = 0, rdt = 80.0, r_scale = 1.0, chol_tol = 0;
+  int64_t workspace = 0;
+};
+
+static int read_opts(const rp_opts *o, Opts &out) {
+  out = Opts();
+  if (o) {
+    if (o->precision != 0 && o->precision != 32 && o->precision != 64)
+      return fail(RP_EINVAL, "precision must be 32 or 64");
+    if (o->precision) out.precision = o->precision;
+    if (o->init_mode != 0 && o->init_mode != 1) return fail(RP_EINVAL, "init_mode must be 0 or 1");
+    out.init_mode = o->init_mode;
+    if (o->tol < 0 || o->rdt < 0 || o->r_scale < 0 || o->workspace_bytes < 0)
+      return fail(RP_EINVAL, "negative option");
+    if ((o->flags & ~RP_FLAG_PROFILE) != 0 || o->reserved != 0)
+      return fail(RP_EINVAL, "unknown flags or nonzero reserved field");
+    out.flags = o->flags;
+    if (o->tol > 0) out.tol = o->tol;
+    if (o->rdt > 0) out.rdt = o->rdt;
+    if (o->r_scale > 0) out.r_scale = o->r_scale;
+    out.workspace = o->workspace_bytes;
+  }
+  if (out.tol == 0) out.tol = out.precision == 64 ? 1e-14 : 1e-9;
+  out.chol_tol = out.precision == 64 ? 1e-17 : 1e-12;
+  if (out.rdt > 4000) return fail(RP_EINVAL, "rdt too large");
+  return RP_OK;
+}
+
+// Plans every field of one system, in parallel over host threads.
+static int plan_all(const SystemSpec &spec, const double *B, int nB, const Opts &op,
+                    std::vector<FieldPlan> &plans) {
+  plans.assign(nB, FieldPlan());
+  std::vector<std::string> msgs(nB);
+  std::vector<char> ok(nB, 0);
+  const int nth = std::max(1, std::min<int>(nB, (int)std::thread::hardware_concurrency()));
+  std::vector<std::thread> th;
+  for (int t = 0; t < nth; ++t)
+    th.emplace_back([&, t]() {
+      for (int b = t; b < nB; b += nth)
+        ok[b] = plan_field(spec, B[b], op.tol, op.rdt, op.r_scale, op.chol_tol, plans[b], msgs[b]);
+    });
+  for (auto &x : th) x.join();
+  for (int b = 0; b < nB; ++b)
+    if (!ok[b]) return fail(RP_EINVAL, "field " + std::to_string(b) + ": " + msgs[b]);
+  return RP_OK;
+}
+
+template <typename R>
+static SysArgs<R> make_sysargs(const SystemSpec &s) {
+  SysArgs<R> a;
+  std::memset(&a, 0, sizeof(a));
+  a.N = s.N();
+  a.N1 = s.N1;
+  a.Z = s.Z;
+  a.J = (R)s.J;
+  // i beta P_S reproduces -i (dk/2) P_x together with the shift (see plan.hpp).
+  a.beta = (R)(s.kS >= s.kT ? -0.5 * (s.kS - s.kT) : 0.5 * (s.kT - s.kS));
+  a.all_half = 1;
+  int64_t st = 1;
+  for (int k = 0; k < a.N; ++k) {
+    a.stride[k] = (int32_t)st;
+    a.d[k] = s.two_I[k] + 1;
+    if (s.two_I[k] != 1) a.all_half = 0;
+    int sh = 0;
+    while ((int64_t(1) << sh) < st) ++sh;
+    a.shift[k] = sh;
+    a.a[k] = (R)s.a[k];
+    const double I = 0.5 * s.two_I[k];
+    for (int n = 0; n < s.two_I[k]; ++n) {
+      const double m = I - n;   // link between m and m-1
+      a.f[k][n] = (R)(0.5 * s.a[k] * std::sqrt(I * (I + 1.0) - m * (m - 1.0)));
+    }
+    st *= a.d[k];
+  }
+  return a;
+}
+
+static unsigned grid1(int64_t n) { return (unsigned)((n + 255) / 256); }
+
+// Propagates every (field, sample) job of one system; writes phi_out[b][s] (device).
+template <typename R>
+static int propagate_system(const SystemSpec &spec, const double *B, int nB, const double *angles_dev,
+                            int64_t M, const Opts &op, double *phi_out, hipStream_t st, EventLog &log) {
+  std::vector<FieldPlan> plans;
+  int rc = plan_all(spec, B, nB, op, plans);
+  if (rc) return rc;
+  const int64_t Z = spec.Z;
+  const int N = spec.N();
+  // Fields sorted by decreasing step count: the jobs still running at any step form a prefix.
+  std::vector<int> order(nB);
+  std::iota(order.begin(), order.end(), 0);
+  std::stable_sort(order.begin(), order.end(),
+                   [&](int a, int b) { return plans[a].n_steps > plans[b].n_steps; });
+  int nt = 1, rk = 1;
+  for (auto &p : plans) {
+    nt = std::max(nt, p.n_terms);
+    rk = std::max(rk, p.rank);
+  }
+  const int rkp = (rk + kQuadChunk - 1) / kQuadChunk * kQuadChunk;
+  std::vector<FieldDev<R>> fdev(nB);
+  std::vector<cx<R>> coef((size_t)nB * nt, cx<R>{R(0), R(0)});
+  std::vector<R> ell((size_t)nB * nt * rkp, R(0));
+  std::vector<double> dts(nB);
+  std::vector<int64_t> nsteps(nB);
+  const double dk = std::fabs(spec.kS - spec.kT);
+  for (int f = 0; f < nB; ++f) {
+    const FieldPlan &p = plans[order[f]];
+    FieldDev<R> d;
+    d.omega = (R)p.omega;
+    d.c_re = (R)p.c_re;
+    d.c_im = (R)(p.c_im + (spec.kS >= spec.kT ? 0.0 : 0.5 * dk));
+    d.s1 = (R)(1.0 / p.r);
+    d.s2 = (R)(2.0 / p.r);
+    fdev[f] = d;
+    for (int n = 0; n < p.n_terms; ++n) coef[(size_t)f * nt + n] = {(R)p.coef[n].real(), (R)p.coef[n].imag()};
+    for (int n = 0; n < p.n_terms; ++n)
+      for (int r = 0; r < p.rank; ++r) ell[((size_t)f * nt + n) * rkp + r] = (R)p.ell[(size_t)n * p.rank + r];
+    dts[f] = p.dt;
+    nsteps[f] = p.n_steps;
+  }
+  const int64_t total_jobs = (int64_t)nB * M;
+  if (total_jobs == 0) return RP_OK;
+  std::vector<int32_t> job_field(total_jobs), job_sample(total_jobs);
+  std::vector<int64_t> dst(total_jobs);
+  for (int f = 0; f < nB; ++f)
+    for (int64_t s = 0; s < M; ++s) {
+      const int64_t j = (int64_t)f * M + s;
+      job_field[j] = f;
+      job_sample[j] = (int32_t)s;
+      dst[j] = (int64_t)order[f] * M + s;
+    }
+  const int64_t nbx = (Z + kBlock - 1) / kBlock;
+  const int64_t vec_bytes = 4 * Z * (int64_t)sizeof(cx<R>);
+  const int64_t per_job = 3 * vec_bytes + (int64_t)nt * Z * sizeof(cx<R>) + nbx * 3 * 8 + 32;
+  int64_t budget = op.workspace;
+  if (budget <= 0) {
+    size_t fr = 0, tot = 0;
+    HIPCHK(hipMemGetInfo(&fr, &tot));
+    budget = (int64_t)(fr / 2);
+  }
+  int64_t chunk = std::min<int64_t>(total_jobs, budget / per_job);
+  if (chunk < 1) return fail(RP_ENOMEM, "workspace too small for one wavepacket");
+  chunk = std::min<int64_t>(chunk, (((int64_t)1) << 24) / nbx);   // grid of < 2^24 workgroups
+
+  // Device allocations.
+  struct Buf {
+    void *p = nullptr;
+    ~Buf() { if (p) (void)hipFree(p); }
+  };
+  Buf bP0, bP1, bP2, bD, bPn, bPq, bPhi, bPrev, bFlag, bFd, bCoef, bEll, bDt, bJf, bJs, bDst, bTab, bOut;
+  auto alloc = [&](Buf &b, size_t bytes) -> int {
+    if (hipMalloc(&b.p, std::max<size_t>(bytes, 16)) != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(RP_ENOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes failed");
+    }
+    return RP_OK;
+  };
+#define ALLOC(b, n)              \
+  do {                           \
+    int rc_ = alloc(b, (n));     \
+    if (rc_) return rc_;         \
+  } while (0)
+  ALLOC(bP0, chunk * vec_bytes);
+  ALLOC(bP1, chunk * vec_bytes);
+  ALLOC(bP2, chunk * vec_bytes);
+  ALLOC(bD, (size_t)nt * chunk * Z * sizeof(cx<R>));
+  ALLOC(bPn, chunk * nbx * 8);
+  ALLOC(bPq, chunk * nbx * 16);
+  ALLOC(bPhi, chunk * 8);
+  ALLOC(bPrev, chunk * 8);
+  ALLOC(bFlag, 16);
+  ALLOC(bFd, nB * sizeof(FieldDev<R>));
+  ALLOC(bCoef, coef.size() * sizeof(cx<R>));
+  ALLOC(bEll, ell.size() * sizeof(R));
+  ALLOC(bDt, nB * 8);
+  ALLOC(bJf, total_jobs * 4);
+  ALLOC(bJs, total_jobs * 4);
+  ALLOC(bDst, total_jobs * 8);
+  ALLOC(bTab, (size_t)std::max<int64_t>(M, 1) * std::max(N, 1) * (RP_MAX_TWO_I + 1) * sizeof(cx<double>));
+#undef ALLOC
+  HIPCHK(hipMemcpyAsync(bFd.p, fdev.data(), nB * sizeof(FieldDev<R>), hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(bCoef.p, coef.data(), coef.size() * sizeof(cx<R>), hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(bEll.p, ell.data(), ell.size() * sizeof(R), hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(bDt.p, dts.data(), nB * 8, hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(bJf.p, job_field.data(), total_jobs * 4, hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(bJs.p, job_sample.data(), total_jobs * 4, hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(bDst.p, dst.data(), total_jobs * 8, hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemsetAsync(bFlag.p, 0, 16, st));
+
+  // Coherent-state components of every sample (shared by all fields).
+  if (N > 0 && M > 0) {
+    CohArgs ca;
+    std::memset(&ca, 0, sizeof(ca));
+    ca.angles = angles_dev;
+    ca.tab = (cx<double> *)bTab.p;
+    ca.M = M;
+    ca.N = N;
+    ca.mode = op.init_mode;
+    for (int k = 0; k < N; ++k) ca.two_I[k] = spec.two_I[k];
+    hipLaunchKernelGGL(k_coherent, dim3(grid1(M * N)), dim3(256), 0, st, ca);
+    HIPCHK(hipGetLastError());
+  }
+  const SysArgs<R> sa = make_sysargs<R>(spec);
+  const double kmin = std::min(spec.kS, spec.kT);
+  const double rtol = op.precision == 64 ? 1e-9 : 1e-4;
+
+  cx<R> *bufs[3] = {(cx<R> *)bP0.p, (cx<R> *)bP1.p, (cx<R> *)bP2.p};
+  for (int64_t j0 = 0; j0 < total_jobs; j0 += chunk) {
+    const int64_t nj = std::min(chunk, total_jobs - j0);
+    const int32_t *jf = (const int32_t *)bJf.p + j0;
+    // initial wavepackets
+    {
+      InitArgs<R> ia;
+      std::memset(&ia, 0, sizeof(ia));
+      ia.psi = bufs[0];
+      ia.tab = (const cx<double> *)bTab.p;
+      ia.job_sample = (const int32_t *)bJs.p + j0;
+      ia.Z = Z;
+      ia.nbx = nbx;
+      ia.njobs = (int32_t)nj;
+      ia.N = N;
+      for (int k = 0; k < N; ++k) {
+        ia.stride[k] = sa.stride[k];
+        ia.d[k] = sa.d[k];
+      }
+      if (N == 0) {
+        ia.stride[0] = 1;
+        ia.d[0] = 1;
+      }
+      hipLaunchKernelGGL(k_init<R>, dim3((unsigned)(nj * nbx)), dim3(kBlock), 0, st, ia);
+      HIPCHK(hipGetLastError());
+    }
+    hipLaunchKernelGGL(k_fill, dim3(grid1(nj)), dim3(256), 0, st, (double *)bPhi.p, nj, 0.0);
+    hipLaunchKernelGGL(k_fill, dim3(grid1(nj)), dim3(256), 0, st, (double *)bPrev.p, nj, 1.0 + 1e-6);
+    HIPCHK(hipGetLastError());
+    int ip = 0, ia_ = 2, iodd = 1;   // psi, accumulator and odd-term buffers
+    const int64_t steps_max = nsteps[job_field[j0]];
+    for (int64_t t = 0; t < steps_max; ++t) {
+      // Jobs of fields with more than t steps form the prefix [0, C(t)) of the sorted list.
+      int64_t nf = 0;
+      while (nf < nB && nsteps[nf] > t) ++nf;
+      const int64_t active = std::min<int64_t>(nj, std::max<int64_t>(0, nf * M - j0));
+      if (active <= 0) break;
+      const unsigned grid = (unsigned)(active * nbx);
+      TermArgs<R> ta;
+      std::memset(&ta, 0, sizeof(ta));
+      ta.fields = (const FieldDev<R> *)bFd.p;
+      ta.coef = (const cx<R> *)bCoef.p;
+      ta.job_field = jf;
+      ta.part_norm = (double *)bPn.p;
+      ta.nbx = nbx;
+      ta.njobs = (int32_t)active;
+      ta.n_terms = nt;
+      ta.acc = bufs[ia_];
+      cx<R> *even = bufs[ip], *odd = bufs[iodd];
+      cx<R> *D = (cx<R> *)bD.p;
+      const int64_t slab = nj * Z;
+      // n = 0: phi_1 = Gh phi_0
+      ta.phin = even;
+      ta.phio = odd;
+      ta.n = 0;
+      ta.dnext = D + slab;
+      ta.dfirst = D;
+      log.mark(st);
+      if (sa.all_half)
+        hipLaunchKernelGGL((k_cheb<R, true, true>), dim3(grid), dim3(kBlock), 0, st, ta, sa);
+      else
+        hipLaunchKernelGGL((k_cheb<R, false, true>), dim3(grid), dim3(kBlock), 0, st, ta, sa);
+      for (int n = 1; n + 1 < nt; ++n) {
+        // phi_{n+1} = 2 Gh phi_n - phi_{n-1}, written over phi_{n-1}
+        ta.phin = (n & 1) ? odd : even;
+        ta.phio = (n & 1) ? even : odd;
+        ta.n = n;
+        ta.dnext = D + (int64_t)(n + 1) * slab;
+        if (sa.all_half)
+          hipLaunchKernelGGL((k_cheb<R, true, false>), dim3(grid), dim3(kBlock), 0, st, ta, sa);
+        else
+          hipLaunchKernelGGL((k_cheb<R, false, false>), dim3(grid), dim3(kBlock), 0, st, ta, sa);
+      }
+      log.mark(st);
+      log.close(0);
+      if (log.on) {
+        g_prof.term_launches += nt - 1;
+        g_prof.elems += (double)(nt - 1) * (double)active * 4.0 * (double)Z;
+        g_prof.quad_launches += 1;
+        g_prof.terms = nt;
+      }
+      HIPCHK(hipGetLastError());
+      QuadArgs<R> qa;
+      std::memset(&qa, 0, sizeof(qa));
+      qa.d = D;
+      qa.slab = slab;
+      qa.ell = (const R *)bEll.p;
+      qa.job_field = jf;
+      qa.part = (double *)bPq.p;
+      qa.Z = Z;
+      qa.nbx = nbx;
+      qa.njobs = (int32_t)active;
+      qa.n_terms = nt;
+      qa.rank_pad = rkp;
+      log.mark(st);
+      hipLaunchKernelGGL(k_quad<R>, dim3(grid), dim3(kBlock), 0, st, qa);
+      log.mark(st);
+      log.close(1);
+      FinArgs fa;
+      fa.part_q = (const double *)bPq.p;
+      fa.part_norm = (const double *)bPn.p;
+      fa.phi = (double *)bPhi.p;
+      fa.prev_norm = (double *)bPrev.p;
+      fa.flag = (int *)bFlag.p;
+      fa.job_field = jf;
+      fa.dt = (const double *)bDt.p;
+      fa.nbx = nbx;
+      fa.njobs = (int32_t)active;
+      fa.step = (int32_t)t;
+      fa.kS = spec.kS;
+      fa.kmin = kmin;
+      fa.rtol = rtol;
+      hipLaunchKernelGGL(k_finalize, dim3(grid1(active)), dim3(256), 0, st, fa);
+      HIPCHK(hipGetLastError());
+      std::swap(ip, ia_);
+    }
+    hipLaunchKernelGGL(k_scatter, dim3(grid1(nj)), dim3(256), 0, st, (const double *)bPhi.p,
+                       (const int64_t *)bDst.p + j0, phi_out, nj);
+    HIPCHK(hipGetLastError());
+  }
+  int flag = 0;
+  HIPCHK(hipMemcpyAsync(&flag, bFlag.p, sizeof(int), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  if (flag) return fail(RP_ENOTCONV, "wavepacket norm grew or became NaN (spectral bound violated)");
+  return RP_OK;
+}
+
+}  // namespace rp
+
+// ============================================================================= C ABI
+using namespace rp;
+
+extern "C" const char *rp_strerror(int code) {
+  switch (code) {
+    case RP_OK: return "ok";
+    case RP_EINVAL: return "invalid argument";
+    case RP_ENOMEM: return "out of device memory";
+    case RP_EDEVICE: return "HIP error";
+    case RP_ENOTCONV: return "propagation did not converge (norm grew)";
+    case RP_ENOTIMPL: return "not implemented";
+    default: return "unknown error";
+  }
+}
+
+extern "C" const char *rp_last_error(void) { return g_err.c_str(); }
+
+extern "C" int rp_bessel_j(double x, int32_t nmax, double *out) {
+  if (!out || nmax < 0 || !(x >= 0.0) || !std::isfinite(x)) return fail(RP_EINVAL, "bad bessel arguments");
+  bessel_j(x, nmax, out);
+  return RP_OK;
+}
+
+extern "C" int rp_plan_field(const rp_system *s, double B_mT, const rp_opts *opts, double *info, double *coef,
+                             double *ell) {
+  int rc = validate_system(s);
+  if (rc) return rc;
+  if (!info) return fail(RP_EINVAL, "null info");
+  Opts op;
+  rc = read_opts(opts, op);
+  if (rc) return rc;
+  const double g = gamma_of(s);
+  SystemSpec spec = make_spec(s->n_nuc[0], s->n_nuc[1], s->two_I, s->a_mT, s->J_mT, s->kS, s->kT, s->T_us, g);
+  FieldPlan p;
+  std::string msg;
+  if (!plan_field(spec, B_mT, op.tol, op.rdt, op.r_scale, op.chol_tol, p, msg)) return fail(RP_EINVAL, msg);
+  info[0] = p.r;
+  info[1] = p.c_re;
+  info[2] = p.c_im;
+  info[3] = p.dt;
+  info[4] = (double)p.n_steps;
+  info[5] = (double)p.n_terms;
+  info[6] = (double)p.rank;
+  info[7] = p.x;
+  if (coef)
+    for (int n = 0; n < p.n_terms; ++n) {
+      coef[2 * n] = p.coef[n].real();
+      coef[2 * n + 1] = p.coef[n].imag();
+    }
+  if (ell) std::memcpy(ell, p.ell.data(), p.ell.size() * sizeof(double));
+  return RP_OK;
+}
+
+extern "C" int rp_sample(const rp_system *s, uint64_t seed, uint32_t stream_id, uint64_t first_sample, int64_t M,
+                         int32_t basis_mode, double *angles, void *hip_stream) {
+  int rc = validate_system(s);
+  if (rc) return rc;
+  if (M < 0) return fail(RP_EINVAL, "M < 0");
+  if (basis_mode < 0 || basis_mode > 2) return fail(RP_EINVAL, "basis_mode must be 0, 1 or 2");
+  const int N = s->n_nuc[0] + s->n_nuc[1];
+  if (M == 0 || N == 0) return RP_OK;
+  if (!angles) return fail(RP_EINVAL, "null angles");
+  if (M > ((int64_t)1 << 40)) return fail(RP_EINVAL, "M too large");
+  SampleArgs a;
+  std::memset(&a, 0, sizeof(a));
+  a.angles = angles;
+  a.seed = seed;
+  a.first = first_sample;
+  a.M = M;
+  a.N = N;
+  a.mode = basis_mode;
+  a.stream = stream_id;
+  int64_t rad = 1;
+  for (int k = 0; k < N; ++k) {
+    a.d[k] = s->two_I[k] + 1;
+    a.radix[k] = rad;
+    rad *= a.d[k];
+  }
+  hipLaunchKernelGGL(k_sample, dim3(grid1(M * N)), dim3(256), 0, (hipStream_t)hip_stream, a);
+  HIPCHK(hipGetLastError());
+  return RP_OK;
+}
+
+extern "C" int rp_propagate(const rp_system *sys, int32_t n_sys, const double *B_mT, int32_t nB,
+                            const double *angles, int64_t M, const rp_opts *opts, double *phi, double *ps_t,
+                            void *hip_stream) {
+  g_err.clear();
+  if (n_sys < 0 || nB < 0 || M < 0) return fail(RP_EINVAL, "negative count");
+  if (n_sys == 0 || nB == 0 || M == 0) return RP_OK;
+  if (!sys || !B_mT || !phi) return fail(RP_EINVAL, "null pointer");
+  if (ps_t) return fail(RP_ENOTIMPL, "trajectory output is not implemented");
+  if (M > (int64_t)1 << 31) return fail(RP_EINVAL, "M too large");
+  Opts op;
+  int rc = read_opts(opts, op);
+  if (rc) return rc;
+  for (int i = 0; i < n_sys; ++i) {
+    rc = validate_system(&sys[i]);
+    if (rc) return rc;
+    if (sys[i].n_nuc[0] + sys[i].n_nuc[1] > 0 && !angles) return fail(RP_EINVAL, "null angles");
+  }
+  for (int64_t i = 0; i < (int64_t)n_sys * nB; ++i)
+    if (!std::isfinite(B_mT[i])) return fail(RP_EINVAL, "non-finite field");
+  hipStream_t st = (hipStream_t)hip_stream;
+  EventLog log;
+  log.on = (op.flags & RP_FLAG_PROFILE) != 0;
+  if (log.on) {
+    g_prof = Profile();
+    g_prof.bytes_per_elem = op.precision == 64 ? 84.0 : 42.0;
+  }
+  hipEvent_t t0 = log.mark(st);
+  int64_t aoff = 0;
+  for (int i = 0; i < n_sys; ++i) {
+    const rp_system *s = &sys[i];
+    const int N = s->n_nuc[0] + s->n_nuc[1];
+    SystemSpec spec = make_spec(s->n_nuc[0], s->n_nuc[1], s->two_I, s->a_mT, s->J_mT, s->kS, s->kT, s->T_us,
+                                gamma_of(s));
+    const double *ang = angles ? angles + aoff : nullptr;
+    double *out = phi + (int64_t)i * nB * M;
+    rc = op.precision == 64 ? propagate_system<double>(spec, B_mT + (int64_t)i * nB, nB, ang, M, op, out, st, log)
+                            : propagate_system<float>(spec, B_mT + (int64_t)i * nB, nB, ang, M, op, out, st, log);
+    if (rc) return rc;
+    aoff += M * N * 2;
+  }
+  if (log.on) {
+    hipEvent_t t1 = nullptr;
+    if (hipEventCreate(&t1) == hipSuccess) {
+      (void)hipEventRecord(t1, st);
+      (void)hipEventSynchronize(t1);
+      float ms = 0.f;
+      if (t0 && hipEventElapsedTime(&ms, t0, t1) == hipSuccess) g_prof.total_ms = ms;
+      (void)hipEventDestroy(t1);
+    }
+    // the first event (t0) is not part of a pair: drop it before resolving pairs
+    if (!log.ev.empty()) {
+      (void)hipEventDestroy(log.ev.front());
+      log.ev.erase(log.ev.begin());
+    }
+    log.resolve(g_prof);
+  }
+  return RP_OK;
+}
+
+extern "C" int rp_profile_last(double *out, int32_t n) {
+  if (!out || n < 0) return fail(RP_EINVAL, "bad profile buffer");
+  const double v[8] = {g_prof.term_ms, g_prof.term_launches, g_prof.elems, g_prof.bytes_per_elem,
+                       g_prof.quad_ms, g_prof.quad_launches, g_prof.total_ms, g_prof.terms};
+  const int m = n < 8 ? n : 8;
+  for (int i = 0; i < m; ++i) out[i] = v[i];
+  return m;
+}
+
+extern "C" int rp_yield(const double *phi, int32_t nB, int64_t M, const double *cv_g, const double *cv_mu,
+                        const double *cv_beta, double *mean, double *stderr_, void *hip_stream) {
+  if (nB < 0 || M < 0) return fail(RP_EINVAL, "negative count");
+  if (nB == 0) return RP_OK;
+  if (M == 0) return fail(RP_EINVAL, "M must be >= 1");
+  if (!phi || !mean || !stderr_) return fail(RP_EINVAL, "null pointer");
+  if (cv_g && (!cv_mu || !cv_beta)) return fail(RP_EINVAL, "control variate needs mu and beta");
+  StatArgs a{phi, cv_g, cv_mu, cv_beta, mean, stderr_, M};
+  hipLaunchKernelGGL(k_stats, dim3(nB), dim3(256), 0, (hipStream_t)hip_stream, a);
+  HIPCHK(hipGetLastError());
+  return RP_OK;
+}

@@ -1,0 +1,193 @@
+"""Python binding of librp (include/rp.h): argument marshalling only.
+
+Every step of the computation runs in the HIP library; PyTorch provides device
+memory and the stream.  Importing this module does not need a GPU; calling a
+device entry point does, and fails loudly if the library is not built.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+from .workloads import GAMMA_E, SpinSystem
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "librp.so")
+
+RP_OK, RP_EINVAL, RP_ENOMEM, RP_EDEVICE, RP_ENOTCONV, RP_ENOTIMPL = 0, -1, -2, -3, -4, -5
+
+
+class RpError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"librp error {code}: {msg}")
+        self.code = code
+
+
+class _System(ctypes.Structure):
+    _fields_ = [("n_nuc", ctypes.c_int32 * 2), ("two_I", ctypes.POINTER(ctypes.c_int32)),
+                ("a_mT", ctypes.POINTER(ctypes.c_double)), ("J_mT", ctypes.c_double),
+                ("kS", ctypes.c_double), ("kT", ctypes.c_double), ("T_us", ctypes.c_double),
+                ("gamma", ctypes.c_double)]
+
+
+class _Opts(ctypes.Structure):
+    _fields_ = [("precision", ctypes.c_int32), ("init_mode", ctypes.c_int32), ("tol", ctypes.c_double),
+                ("rdt", ctypes.c_double), ("r_scale", ctypes.c_double), ("workspace_bytes", ctypes.c_int64),
+                ("flags", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+_lib = None
+
+EXPORTS = ["rp_sample", "rp_propagate", "rp_yield", "rp_strerror", "rp_last_error", "rp_bessel_j",
+           "rp_plan_field", "rp_profile_last"]
+RP_FLAG_PROFILE = 1
+
+
+def lib():
+    """The loaded library; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, dp, i32, i64, u32, u64 = (ctypes.c_void_p, ctypes.POINTER(ctypes.c_double), ctypes.c_int32,
+                                      ctypes.c_int64, ctypes.c_uint32, ctypes.c_uint64)
+        sp = ctypes.POINTER(_System)
+        op = ctypes.POINTER(_Opts)
+        L.rp_sample.argtypes = [sp, u64, u32, u64, i64, i32, vp, vp]
+        L.rp_propagate.argtypes = [sp, i32, dp, i32, vp, i64, op, vp, vp, vp]
+        L.rp_yield.argtypes = [vp, i32, i64, vp, vp, vp, vp, vp, vp]
+        L.rp_strerror.argtypes = [ctypes.c_int]
+        L.rp_strerror.restype = ctypes.c_char_p
+        L.rp_last_error.restype = ctypes.c_char_p
+        L.rp_bessel_j.argtypes = [ctypes.c_double, i32, dp]
+        L.rp_plan_field.argtypes = [sp, ctypes.c_double, op, dp, dp, dp]
+        L.rp_profile_last.argtypes = [dp, i32]
+        for f in ("rp_sample", "rp_propagate", "rp_yield", "rp_bessel_j", "rp_plan_field", "rp_profile_last"):
+            getattr(L, f).restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def _check(code):
+    if code != RP_OK:
+        L = lib()
+        raise RpError(code, f"{L.rp_strerror(code).decode()}: {L.rp_last_error().decode()}")
+
+
+class _CSystem:
+    """Keeps the host arrays of one rp_system alive while a call runs."""
+
+    def __init__(self, s: SpinSystem):
+        self.two_I = np.ascontiguousarray(s.two_I if s.N else [0], np.int32)
+        self.a = np.ascontiguousarray(s.a_mT if s.N else [0.0], np.float64)
+        self.c = _System()
+        self.c.n_nuc[0], self.c.n_nuc[1] = s.n1, s.n2
+        self.c.two_I = self.two_I.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+        self.c.a_mT = self.a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        self.c.J_mT, self.c.kS, self.c.kT, self.c.T_us = s.J_mT, s.kS, s.kT, s.T_us
+        self.c.gamma = s.gamma if s.gamma else GAMMA_E
+
+
+def _opts(precision=64, init_mode=0, tol=0.0, rdt=0.0, r_scale=0.0, workspace_bytes=0, flags=0):
+    o = _Opts()
+    o.precision, o.init_mode, o.tol, o.rdt, o.r_scale = precision, init_mode, tol, rdt, r_scale
+    o.workspace_bytes, o.flags, o.reserved = workspace_bytes, flags, 0
+    return o
+
+
+def _stream(torch):
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _dev_ptr(t, dtype):
+    import torch
+    if t is None:
+        return None
+    if not t.is_cuda or t.dtype != dtype or not t.is_contiguous():
+        raise ValueError("expected a contiguous CUDA tensor of dtype %s" % dtype)
+    return ctypes.c_void_p(t.data_ptr())
+
+
+# ----------------------------------------------------------------------------- device entry points
+def sample(system: SpinSystem, seed, M, first=0, stream_id=0, basis_mode=0, out=None):
+    """rp_sample: [M][N][2] float64 CUDA tensor of directions (or basis digits)."""
+    import torch
+    cs = _CSystem(system)
+    if out is None:
+        out = torch.empty((M, system.N, 2), dtype=torch.float64, device="cuda")
+    _check(lib().rp_sample(ctypes.byref(cs.c), seed, stream_id, first, M, basis_mode,
+                           _dev_ptr(out, torch.float64), _stream(torch)))
+    return out
+
+
+def propagate(systems, B_mT, angles, M, precision=64, init_mode=0, tol=0.0, rdt=0.0, r_scale=0.0,
+              workspace_bytes=0, out=None, profile=False):
+    """rp_propagate: single-wavepacket yields [n_sys][nB][M] (float64 CUDA tensor).
+
+    ``systems`` is a SpinSystem or a list; ``B_mT`` is [n_sys][nB] (host);
+    ``angles`` is the concatenation of the per-system [M][N][2] arrays (CUDA).
+    """
+    import torch
+    if isinstance(systems, SpinSystem):
+        systems = [systems]
+    B = np.ascontiguousarray(np.atleast_2d(np.asarray(B_mT, np.float64)))
+    if B.shape[0] != len(systems):
+        raise ValueError("B_mT must have one row per system")
+    nB = B.shape[1]
+    cs = [_CSystem(s) for s in systems]
+    arr = (_System * len(cs))(*[c.c for c in cs])
+    if out is None:
+        out = torch.empty((len(systems), nB, M), dtype=torch.float64, device="cuda")
+    ang = _dev_ptr(angles, torch.float64) if angles is not None and angles.numel() else None
+    o = _opts(precision, init_mode, tol, rdt, r_scale, workspace_bytes, RP_FLAG_PROFILE if profile else 0)
+    _check(lib().rp_propagate(arr, len(cs), B.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), nB, ang, M,
+                              ctypes.byref(o), _dev_ptr(out, torch.float64), None, _stream(torch)))
+    return out
+
+
+def yield_stats(phi, cv_g=None, cv_mu=None, cv_beta=None):
+    """rp_yield: per-field mean and standard error of phi [nB][M] (CUDA float64)."""
+    import torch
+    phi = phi.reshape(-1, phi.shape[-1]).contiguous()
+    nB, M = phi.shape
+    mean = torch.empty(nB, dtype=torch.float64, device="cuda")
+    err = torch.empty(nB, dtype=torch.float64, device="cuda")
+    g = _dev_ptr(cv_g.reshape(nB, M).contiguous(), torch.float64) if cv_g is not None else None
+    mu = _dev_ptr(cv_mu.contiguous(), torch.float64) if cv_mu is not None else None
+    be = _dev_ptr(cv_beta.contiguous(), torch.float64) if cv_beta is not None else None
+    _check(lib().rp_yield(_dev_ptr(phi, torch.float64), nB, M, g, mu, be, _dev_ptr(mean, torch.float64),
+                          _dev_ptr(err, torch.float64), _stream(torch)))
+    return mean, err
+
+
+def profile_last():
+    """Timing totals of the last profiled rp_propagate call on this thread (see rp.h)."""
+    out = np.zeros(8)
+    lib().rp_profile_last(out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), 8)
+    keys = ["term_ms", "term_launches", "elements", "bytes_per_element", "quad_ms", "quad_launches",
+            "total_ms", "terms_per_step"]
+    return dict(zip(keys, out.tolist()))
+
+
+# ----------------------------------------------------------------------------- host-only helpers
+def bessel_j(x, nmax):
+    out = np.zeros(nmax + 1)
+    _check(lib().rp_bessel_j(float(x), int(nmax), out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+    return out
+
+
+def plan_field(system: SpinSystem, B_mT, precision=64, tol=0.0, rdt=0.0, r_scale=0.0):
+    """Chebyshev step plan of one field: dict with r, c, dt, n_steps, n_terms, rank, x, coef, ell."""
+    cs = _CSystem(system)
+    o = _opts(precision, 0, tol, rdt, r_scale)
+    info = np.zeros(8)
+    dp = ctypes.POINTER(ctypes.c_double)
+    _check(lib().rp_plan_field(ctypes.byref(cs.c), float(B_mT), ctypes.byref(o), info.ctypes.data_as(dp),
+                               None, None))
+    nt, rk = int(info[5]), int(info[6])
+    coef = np.zeros(2 * nt)
+    ell = np.zeros(nt * rk)
+    _check(lib().rp_plan_field(ctypes.byref(cs.c), float(B_mT), ctypes.byref(o), info.ctypes.data_as(dp),
+                               coef.ctypes.data_as(dp), ell.ctypes.data_as(dp)))
+    return dict(r=info[0], c=complex(info[1], info[2]), dt=info[3], n_steps=int(info[4]), n_terms=nt,
+                rank=rk, x=info[7], coef=coef[0::2] + 1j * coef[1::2], ell=ell.reshape(nt, rk))

@@ -1,0 +1,154 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle, element by element
+on identical seeded inputs.  Tolerances: relative 1e-10 per yield for complex-FP64
+wavepackets, 1e-5 for complex-FP32 wavepackets with FP64 reductions."""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import philox, stats
+from paper_1612_09517_amd import rp, workloads
+from paper_1612_09517_amd.workloads import SpinSystem
+
+import gpu_common as gc
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+TOL = {64: 1e-10, 32: 1e-5}
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _device():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    rp.lib()   # raises if the library is missing
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _rel(got, want):
+    return np.max(np.abs(got - want) / np.maximum(np.abs(want), 1e-300))
+
+
+# --------------------------------------------------------------------------- sampler
+@pytest.mark.parametrize("mode", [0, 1, 2])
+def test_sampler_bit_exact(mode):
+    s = SpinSystem(3, 2, [1, 2, 1, 4, 1], [0.1] * 5)
+    _say("sampler mode", mode)
+    got = rp.sample(s, seed=1234, M=37, first=5, stream_id=2, basis_mode=mode).cpu().numpy()
+    if mode == 0:
+        want = philox.sample_angles(1234, 5, 37, 5, stream=2)
+    elif mode == 1:
+        want = philox.sample_basis_digits(1234, 5, 37, s.two_I, stream=2)
+    else:
+        want = philox.enumerate_basis_digits(5, 37, s.two_I)
+    assert np.array_equal(got, want)
+
+
+# --------------------------------------------------------------------------- tiny workload (Z = 8)
+@pytest.mark.parametrize("prec", [64, 32])
+def test_tiny_workload_parity(prec):
+    w = workloads.tiny_c1()
+    s = w.systems[0]
+    _say("tiny workload parity, precision", prec)
+    ang = rp.sample(s, w.seed, w.M)
+    phi = rp.propagate(s, w.fields_mT, ang, w.M, precision=prec).cpu().numpy()[0]
+    want = gc.oracle_phi(s, w.fields_mT[0], philox.sample_angles(w.seed, 0, w.M, s.N))
+    assert _rel(phi, want) < TOL[prec]
+
+
+@pytest.mark.parametrize("prec", [64, 32])
+def test_general_spins_exchange_triplet_dissipation(prec):
+    """Spin-1 nucleus (mixed radix), J != 0 and kT > kS (P_T is the dissipative projector)."""
+    s = SpinSystem(2, 1, [1, 2, 1], [0.8, -0.3, 0.5], J_mT=0.4, kS=0.5, kT=2.0, T_us=3.0)
+    B = np.array([[0.0, 1.7, 4.0]])
+    _say("general spins, precision", prec)
+    ang = rp.sample(s, 77, 8)
+    phi = rp.propagate(s, B, ang, 8, precision=prec).cpu().numpy()[0]
+    want = gc.oracle_phi(s, B[0], philox.sample_angles(77, 0, 8, 3))
+    assert _rel(phi, want) < TOL[prec]
+
+
+def test_deterministic_trace_by_enumeration():
+    """Basis states |S, M> (init_mode 1) over all Z give the Eq. 14 trace."""
+    w = workloads.tiny_c1()
+    s = w.systems[0]
+    B = np.array([[0.0, 1.0, 5.0]])
+    _say("enumerated trace")
+    dig = rp.sample(s, 0, s.Z, basis_mode=2)
+    phi = rp.propagate(s, B, dig, s.Z, init_mode=1).cpu().numpy()[0]
+    want = gc.oracle_phi(s, B[0], philox.enumerate_basis_digits(0, s.Z, s.two_I), basis=True)
+    assert _rel(phi, want) < 1e-10
+    for b, Bv in enumerate(B[0]):
+        assert abs(phi[b].mean() - gc.oracle_trace(s, Bv)) < 1e-10
+
+
+def test_no_nuclei_closed_form():
+    s = SpinSystem(0, 0, [], [], J_mT=0.9, kS=1.3, kT=0.2, T_us=2.5)
+    _say("no nuclei")
+    phi = rp.propagate(s, np.array([[0.0, 3.0]]), None, 4).cpu().numpy()[0]
+    assert np.max(np.abs(phi - (1 - math.exp(-1.3 * 2.5)))) < 1e-12
+
+
+# --------------------------------------------------------------------------- several tiles, ragged tail
+def test_multi_block_ragged_mixed_radix():
+    """Z = 2^9 * 3 = 1536 nuclear states: six 256-thread tiles per wavepacket, spin-1 slowest."""
+    rng = np.random.default_rng(5)
+    a = list(rng.uniform(-0.4, 0.4, 10))
+    s = SpinSystem(5, 5, [1] * 9 + [2], a, J_mT=0.2, kS=1.5, kT=0.5, T_us=0.6)
+    B = np.array([[0.0, 2.0]])
+    _say("multi-block ragged, Z =", s.Z)
+    ang = rp.sample(s, 9, 3)
+    want = gc.oracle_phi_sparse(s, B[0], philox.sample_angles(9, 0, 3, s.N))
+    for prec in (64, 32):
+        phi = rp.propagate(s, B, ang, 3, precision=prec).cpu().numpy()[0]
+        assert _rel(phi, want) < TOL[prec] * (10 if prec == 64 else 1)
+
+
+# --------------------------------------------------------------------------- batching and chunking
+def test_multi_system_call_and_chunking_are_consistent():
+    w = workloads.tiny_c1()
+    s1 = w.systems[0]
+    s2 = SpinSystem(1, 2, [2, 1, 1], [0.6, 0.2, -0.7], kS=2.0, kT=0.7, T_us=4.0)
+    B = np.array([[0.0, 2.0, 4.5], [1.0, 0.5, 3.0]])
+    _say("multi-system")
+    a1, a2 = rp.sample(s1, 3, 6), rp.sample(s2, 4, 6)
+    both = rp.propagate([s1, s2], B, torch.cat([a1.reshape(-1), a2.reshape(-1)]), 6).cpu().numpy()
+    one = rp.propagate(s1, B[:1], a1, 6).cpu().numpy()[0]
+    two = rp.propagate(s2, B[1:], a2, 6).cpu().numpy()[0]
+    assert np.array_equal(both[0], one) and np.array_equal(both[1], two)
+    small = rp.propagate(s2, B[1:], a2, 6, workspace_bytes=3 * 2 * 6000).cpu().numpy()[0]
+    assert np.array_equal(small, two)
+    again = rp.propagate(s2, B[1:], a2, 6).cpu().numpy()[0]
+    assert np.array_equal(again, two)
+
+
+# --------------------------------------------------------------------------- statistics and errors
+def test_yield_statistics():
+    rng = np.random.default_rng(2)
+    phi = rng.uniform(0, 1, (5, 33))
+    g = phi + rng.normal(0, 0.1, phi.shape)
+    mu = rng.uniform(0, 1, 5)
+    be = rng.uniform(0, 1, 5)
+    T = lambda x: torch.tensor(x, dtype=torch.float64, device="cuda")
+    m, e = rp.yield_stats(T(phi))
+    wm, we = stats.mc_mean_error(phi)
+    assert np.max(np.abs(m.cpu().numpy() - wm)) < 1e-14 and np.max(np.abs(e.cpu().numpy() - we)) < 1e-14
+    m, e = rp.yield_stats(T(phi), T(g), T(mu), T(be))
+    wm, we = stats.cv_mean_error(phi, g, mu, be)
+    assert np.max(np.abs(m.cpu().numpy() - wm)) < 1e-14 and np.max(np.abs(e.cpu().numpy() - we)) < 1e-14
+
+
+def test_underestimated_spectrum_is_reported():
+    w = workloads.tiny_c1()
+    s = w.systems[0]
+    _say("notconv")
+    ang = rp.sample(s, 1, 2)
+    with pytest.raises(rp.RpError) as ei:
+        rp.propagate(s, np.array([[4.0]]), ang, 2, r_scale=0.3)
+    assert ei.value.code == rp.RP_ENOTCONV

@@ -1,0 +1,128 @@
+"""Host-side checks of librp that need no GPU: exports, argument validation and the
+Chebyshev/quadrature plan (Bessel coefficients, in-step quadrature factor), the
+latter checked by driving a dense CPU emulation of the propagation with the
+library's own plan and comparing against the oracle."""
+import ctypes
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+import scipy.special as ss
+
+from oracle import coherent, philox, spin, yields
+from paper_1612_09517_amd import rp
+from paper_1612_09517_amd.workloads import SpinSystem
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "rp.h")).read()
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?\w+\s*\*?\s*(rp_\w+)\s*\(", src, re.M)))
+
+
+def test_header_declares_expected_entry_points():
+    assert set(_declared()) == set(rp.EXPORTS)
+
+
+def test_library_loads_and_exports_every_declared_symbol():
+    L = rp.lib()
+    for name in _declared():
+        assert hasattr(L, name), name
+
+
+@pytest.mark.parametrize("x", [0.0, 1e-3, 0.7, 5.0, 39.9, 80.0, 200.0, 600.0])
+def test_bessel_matches_scipy(x):
+    nmax = int(x) + 60
+    got = rp.bessel_j(x, nmax)
+    want = ss.jv(np.arange(nmax + 1), x)
+    assert np.max(np.abs(got - want)) < 2e-14 * max(1.0, math.sqrt(x) / 3)
+
+
+def _sys(**kw):
+    d = dict(n1=2, n2=1, two_I=[1, 1, 1], a_mT=[0.8, 0.3, 0.5], J_mT=0.0, kS=1.0, kT=1.0, T_us=10.0)
+    d.update(kw)
+    return SpinSystem(**d)
+
+
+def test_plan_coefficients_are_bessel_series():
+    s = _sys(kS=2.0, kT=0.5)
+    p = rp.plan_field(s, 1.0)
+    n = np.arange(p["n_terms"])
+    want = np.where(n == 0, 1.0, 2.0) * (-1j) ** n * ss.jv(n, p["x"]) * np.exp(-1j * p["c"] * p["dt"])
+    assert np.max(np.abs(p["coef"] - want)) < 1e-14
+    assert abs(p["c"] - (-0.25j * 1.5)) < 1e-15
+    assert abs(p["n_steps"] * p["dt"] - s.T_us) < 1e-12
+    assert abs(p["x"] - p["r"] * p["dt"]) < 1e-12
+    assert p["x"] <= 80.0 + 1e-9
+
+
+def test_plan_quadrature_factor():
+    """ell ell^T equals (2-d_m0)(2-d_n0)/2 int_0^dt J_m(rs) J_n(rs) exp(-(kS+kT)s/2) ds."""
+    s = _sys(kS=2.0, kT=0.5)
+    p = rp.plan_field(s, 0.3, rdt=12.0)
+    nt = p["n_terms"]
+    xg, wg = np.polynomial.legendre.leggauss(200)
+    sq = 0.5 * p["dt"] * (xg + 1)
+    w = 0.5 * p["dt"] * wg * np.exp(-1.25 * sq)
+    Jm = ss.jv(np.arange(nt)[:, None], p["r"] * sq[None, :])
+    K = (Jm * w) @ Jm.T
+    f = np.where(np.arange(nt) == 0, 1.0, 2.0) / math.sqrt(2)
+    assert np.max(np.abs(p["ell"] @ p["ell"].T - np.outer(f, f) * K)) < 1e-15 * 4 * p["dt"] + 1e-17
+
+
+def _emulate(sysd, B, angles, precision=64):
+    """Dense CPU emulation of the GPU algorithm, driven by the library's plan."""
+    d = spin.DenseSystem((sysd.n1, sysd.n2), sysd.two_I, sysd.a_mT, J_mT=sysd.J_mT, kS=sysd.kS, kT=sysd.kT)
+    p = rp.plan_field(sysd, B, precision=precision)
+    kmin = min(sysd.kS, sysd.kT)
+    Gp = d.G(B) + 0.5j * kmin * np.eye(d.dim)
+    Gh = (Gp - p["c"] * np.eye(d.dim)) / p["r"]
+    psi = coherent.initial_wavepacket(d, angles)
+    out = 0.0
+    for j in range(p["n_steps"]):
+        ph = [psi, Gh @ psi]
+        for _ in range(2, p["n_terms"]):
+            ph.append(2 * Gh @ ph[-1] - ph[-2])
+        # singlet amplitude times sqrt 2 in the oracle's ordering (S1, S2, nuclei)
+        amp = np.array([np.kron(d.singlet * math.sqrt(2), np.eye(d.Z)).conj() @ v for v in ph])
+        rot = (-1j) ** np.arange(p["n_terms"])
+        W = p["ell"].T @ (rot[:, None] * amp)
+        out += sysd.kS * math.exp(-kmin * j * p["dt"]) * np.sum(np.abs(W) ** 2)
+        psi = sum(a * v for a, v in zip(p["coef"], ph))
+    return out
+
+
+@pytest.mark.parametrize("kS,kT,J,B", [(1.0, 1.0, 0.0, 0.0), (2.0, 0.5, 0.0, 3.0), (0.3, 2.5, 0.6, 1.0)])
+def test_plan_drives_exact_yield(kS, kT, J, B):
+    sysd = _sys(kS=kS, kT=kT, J_mT=J, T_us=2.0)
+    d = spin.DenseSystem((sysd.n1, sysd.n2), sysd.two_I, sysd.a_mT, J_mT=J, kS=kS, kT=kT)
+    fo = yields.FieldOracle(d, B, sysd.T_us)
+    for a in philox.sample_angles(4, 0, 2, 3):
+        want = fo.phi(coherent.initial_wavepacket(d, a))
+        assert abs(_emulate(sysd, B, a) - want) < 1e-11 * want
+
+
+def test_argument_validation_without_device():
+    L = rp.lib()
+    good = _sys()
+    cs = rp._CSystem(good)
+    bad = rp._CSystem(_sys(kS=-1.0))
+    B = np.zeros(2)
+    dp = B.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    fake = ctypes.c_void_p(16)
+    assert L.rp_propagate(ctypes.byref(bad.c), 1, dp, 2, fake, 4, None, fake, None, None) == rp.RP_EINVAL
+    assert L.rp_propagate(ctypes.byref(cs.c), 1, dp, 2, fake, 4, None, fake, fake, None) == rp.RP_ENOTIMPL
+    assert L.rp_propagate(ctypes.byref(cs.c), 1, None, 2, fake, 4, None, fake, None, None) == rp.RP_EINVAL
+    o = rp._opts(precision=16)
+    assert L.rp_propagate(ctypes.byref(cs.c), 1, dp, 2, fake, 4, ctypes.byref(o), fake, None, None) == rp.RP_EINVAL
+    assert L.rp_sample(ctypes.byref(cs.c), 1, 0, 0, -1, 0, fake, None) == rp.RP_EINVAL
+    assert L.rp_sample(ctypes.byref(cs.c), 1, 0, 0, 4, 7, fake, None) == rp.RP_EINVAL
+    big = rp._CSystem(SpinSystem(1, 0, [5], [0.1]))
+    assert L.rp_sample(ctypes.byref(big.c), 1, 0, 0, 4, 0, fake, None) == rp.RP_EINVAL
+    assert L.rp_yield(None, 3, 4, None, None, None, fake, fake, None) == rp.RP_EINVAL
+    assert L.rp_yield(fake, 3, 4, fake, None, None, fake, fake, None) == rp.RP_EINVAL
+    assert b"two_I" in L.rp_last_error() or len(L.rp_last_error()) > 0
+    assert L.rp_strerror(rp.RP_ENOTCONV).startswith(b"propagation")
