@@ -41,14 +41,48 @@ def cpu_baseline(w, seconds_target=20.0):
         large.yield_augmented(sp, B, s.T_us * frac, psi, tau=1.0)
         dt = time.perf_counter() - t0
     rate = frac / dt
-    try:
-        import threadpoolctl
-        cores = max(x.get("num_threads", 1) for x in threadpoolctl.threadpool_info()) if threadpoolctl.threadpool_info() else 1
-    except Exception:
-        cores = 1
-    return {"value": rate, "unit": "propagations/s", "cores": int(cores), "kind": "oracle",
+    # The oracle's hot loop is scipy's CSR sparse matrix-vector product, which runs on one core.
+    return {"value": rate, "unit": "propagations/s", "cores": 1, "kind": "oracle",
             "sample": f"one wavepacket at B={B:.3f} mT over {frac * s.T_us:.3g} of {s.T_us} us "
-                      f"({dt:.1f} s), scaled linearly to the full horizon"}
+                      f"({dt:.1f} s), scaled linearly to the full horizon; host has {os.cpu_count()} cores"}
+
+
+def measured_traffic(precision, terms_per_step, elements_per_launch):
+    """HBM bytes per term launch from the committed counter summary, or None when the
+    kernel source has changed since the counters were taken (or for FP64, not measured)."""
+    import hashlib
+    f = os.path.join(ROOT, "profiles", "k_cheb_half_c2_traffic.json")
+    if precision != 32 or not os.path.exists(f):
+        return None
+    doc = json.load(open(f))
+    src = os.path.join(ROOT, "paper_1612_09517_amd", "csrc", "rp.hip")
+    if hashlib.sha256(open(src, "rb").read()).hexdigest() != doc["rp_hip_sha256"]:
+        return None
+    t = doc["per_launch_type"]
+    n_acc3 = (terms_per_step - 2) // 3
+    n_plain = terms_per_step - 2 - n_acc3
+    per_elem = (t["first"]["total"] + n_plain * t["plain"]["total"] + n_acc3 * t["acc3"]["total"]) / (terms_per_step - 1)
+    return per_elem * elements_per_launch
+
+
+def summarize(path):
+    """Per-kernel summary of a rocprofv3 CSV output directory (kernel stats and/or counters)."""
+    import csv
+    import glob
+    from collections import defaultdict
+    out = {}
+    for f in glob.glob(os.path.join(path, "*kernel_stats.csv")):
+        for r in csv.DictReader(open(f)):
+            out.setdefault(r["Name"], {}).update(
+                {"calls": int(r["Calls"]), "avg_us": float(r["AverageNs"]) / 1e3, "pct": float(r["Percentage"])})
+    for f in glob.glob(os.path.join(path, "*counter_collection.csv")):
+        acc = defaultdict(list)
+        for r in csv.DictReader(open(f)):
+            acc[(r["Kernel_Name"], r["Counter_Name"])].append(float(r["Counter_Value"]))
+        for (k, c), v in acc.items():
+            out.setdefault(k, {})[c + "_KiB_avg"] = sum(v) / len(v)
+            out[k][c + "_dispatches"] = len(v)
+    return out
 
 
 def main():
@@ -60,8 +94,28 @@ def main():
     ap.add_argument("--fields", type=int, default=64)
     ap.add_argument("--precision", type=int, default=32, choices=[32, 64])
     ap.add_argument("--rdt", type=float, default=0.0)
+    ap.add_argument("--workspace-gb", type=float, default=0.0,
+                    help="device workspace cap per call (bounds how many wavepackets run together)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe", type=float, default=0.0,
+                    help="only copy a buffer of this many GiB three times (calibrates HBM counters)")
+    ap.add_argument("--summarize", default="",
+                    help="print a per-kernel summary of a rocprofv3 CSV directory and exit")
     args = ap.parse_args()
+    if args.summarize:
+        for k, v in sorted(summarize(args.summarize).items(), key=lambda kv: -kv[1].get("pct", 0)):
+            print(json.dumps({"kernel": k, **v}))
+        return
+    if args.copy_probe > 0:
+        import torch
+        n = int(args.copy_probe * 2 ** 30) // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes_each_way": 4 * n, "copies": 3}), flush=True)
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only; multi-GPU runs are not part of "
                                    "this build (the sweep would shard jobs across GPUs with one final "
@@ -81,7 +135,8 @@ def main():
 
     def step(i, profile=False):
         ang = rp.sample(s, w.seed, Mb, first=i * Mb)
-        phi = rp.propagate(s, B, ang, Mb, precision=args.precision, rdt=args.rdt, profile=profile)
+        phi = rp.propagate(s, B, ang, Mb, precision=args.precision, rdt=args.rdt, profile=profile,
+                           workspace_bytes=int(args.workspace_gb * 2 ** 30))
         mean, err = rp.yield_stats(phi[0])
         return phi, mean, err
 
@@ -126,7 +181,10 @@ def main():
                    "Z": s.Z, "dim": s.dim, "fields": int(B.shape[1]), "samples_per_step": Mb,
                    "precision": f"complex-FP{args.precision} state, FP64 coefficients and reductions"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                     "frac": achieved / PEAK_HBM_GBS, "traffic": None,
+                     "frac": achieved / PEAK_HBM_GBS,
+                     "traffic": measured_traffic(args.precision, int(nterms),
+                                                 prof["elements"] / max(prof["term_launches"], 1)),
+                     "algorithmic_bytes_per_launch": prof["elements"] * bpe / max(prof["term_launches"], 1),
                      "kernel": "k_cheb (Chebyshev term)", "avg_launch_us": prof["term_ms"] * 1e3 / max(prof["term_launches"], 1),
                      "bytes_per_element_term": bpe, "terms_per_step": nterms,
                      "term_time_frac": prof["term_ms"] / max(prof["total_ms"], 1e-9),

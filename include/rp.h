@@ -144,9 +144,11 @@ int rp_yield(const double *phi, int32_t nB, int64_t M, const double *cv_g, const
  *   [0] milliseconds spent in Chebyshev-term kernels (events on the call's stream)
  *   [1] number of Chebyshev-term kernel launches
  *   [2] wavepacket elements processed by them (sum over launches of jobs * 4Z)
- *   [3] algorithmic bytes per element and term: read phi_n, phi_{n-1} and the step
- *       accumulator, write phi_{n+1} and the accumulator (5 complex numbers) plus the
- *       singlet amplitude (1/4 complex per element): 42 (complex FP32) or 84 (FP64)
+ *   [3] algorithmic bytes per element and term, averaged over the launches: a term
+ *       reads phi_n and phi_{n-1} and writes phi_{n+1} and the singlet amplitude
+ *       (26 bytes per element for complex FP32); every third term also reads and
+ *       writes the step accumulator (+16); the first term of a step reads phi_0 and
+ *       writes phi_1, the accumulator and two amplitudes (28).  Doubled for FP64.
  *   [4] milliseconds in the in-step quadrature kernels, [5] their launches
  *   [6] milliseconds of the whole call, [7] Chebyshev terms per step (padded maximum)
  * Returns the number of values written.

@@ -1,10 +1,12 @@
 // Device-side data structures and kernels of librp (gfx950, wave64).
 //
 // Wavepacket layout in HBM: one job (system, field, sample) owns a contiguous
-// vector of 4Z complex numbers, element index  e + 4 M,  where e = 2 b1 + b2
-// enumerates the electron product states (aa, ab, ba, bb) with b = 1 for beta,
-// and M = sum_k n_k stride_k is the mixed-radix nuclear index with digit
-// n_k = I_k - m_k (first nucleus fastest).  Interleaved (re, im).
+// vector of 4Z complex numbers stored as four planes, element index  e Z + M,
+// where e = 2 b1 + b2 enumerates the electron product states (aa, ab, ba, bb)
+// with b = 1 for beta, and M = sum_k n_k stride_k is the mixed-radix nuclear
+// index with digit n_k = I_k - m_k (first nucleus fastest).  Each complex number
+// is interleaved (re, im).  Planes make every partner read along a slow nuclear
+// axis a unit-stride load of exactly the two components it needs.
 #pragma once
 
 #include <hip/hip_runtime.h>

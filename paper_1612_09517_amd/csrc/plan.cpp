@@ -62,6 +62,143 @@ double spectral_radius_bound(const SystemSpec &s, double omega) {
   return rho;
 }
 
+// H_i = omega S_z + sum_{k in radical i} a_k I_k.S on one radical (electron fastest,
+// then the radical's nuclei in mixed radix, first fastest): y = H_i x.
+struct RadicalOp {
+  int n = 0;
+  int64_t dim = 2;
+  std::vector<int64_t> stride;
+  std::vector<int> d;
+  std::vector<double> a, twoI;
+  double omega = 0.0;
+  void apply(const double *x, double *y) const {
+    for (int64_t i = 0; i < dim; ++i) y[i] = 0.0;
+    for (int64_t m = 0; m < dim / 2; ++m) {
+      double h = omega;
+      for (int k = 0; k < n; ++k) {
+        const int dig = (int)((m / stride[k]) % d[k]);
+        const double I = 0.5 * twoI[k], mk = I - dig;
+        h += a[k] * mk;
+        if (dig + 1 < d[k]) {   // |alpha, m_k-1> -> |beta, m_k> by (a/2) I+ S-, and back
+          const double f = 0.5 * a[k] * std::sqrt(I * (I + 1.0) - mk * (mk - 1.0));
+          const int64_t p = m + stride[k];
+          y[2 * m + 1] += f * x[2 * p];
+          y[2 * p] += f * x[2 * m + 1];
+        }
+      }
+      y[2 * m] += 0.5 * h * x[2 * m];
+      y[2 * m + 1] -= 0.5 * h * x[2 * m + 1];
+    }
+  }
+};
+
+// Number of eigenvalues of the symmetric tridiagonal (alpha, beta) below t (Sturm count).
+static int sturm_count(const std::vector<double> &al, const std::vector<double> &be, double t) {
+  int c = 0;
+  double q = 1.0;
+  for (size_t j = 0; j < al.size(); ++j) {
+    const double b2 = j ? be[j - 1] * be[j - 1] : 0.0;
+    q = al[j] - t - (j ? b2 / q : 0.0);
+    if (q == 0.0) q = -1e-300;
+    if (q < 0.0) ++c;
+  }
+  return c;
+}
+
+// Extreme eigenvalues of a radical Hamiltonian by Lanczos with full reorthogonalisation.
+static bool radical_extremes(const RadicalOp &op, double &lo, double &hi) {
+  const int64_t n = op.dim;
+  const int mmax = (int)std::min<int64_t>(n, 90);
+  std::vector<std::vector<double>> Q;
+  std::vector<double> al, be, v(n), w(n);
+  uint64_t st = 0x9E3779B97F4A7C15ull;
+  double nr = 0.0;
+  for (int64_t i = 0; i < n; ++i) {   // deterministic pseudo-random start vector
+    st ^= st << 13;
+    st ^= st >> 7;
+    st ^= st << 17;
+    v[i] = ((double)(st >> 11) * 0x1p-53) - 0.5;
+    nr += v[i] * v[i];
+  }
+  nr = std::sqrt(nr);
+  for (auto &x : v) x /= nr;
+  double prev_hi = 0, prev_lo = 0;
+  for (int j = 0; j < mmax; ++j) {
+    Q.push_back(v);
+    op.apply(v.data(), w.data());
+    double a = 0.0;
+    for (int64_t i = 0; i < n; ++i) a += w[i] * v[i];
+    al.push_back(a);
+    for (int pass = 0; pass < 2; ++pass)
+      for (const auto &q : Q) {
+        double c = 0.0;
+        for (int64_t i = 0; i < n; ++i) c += w[i] * q[i];
+        for (int64_t i = 0; i < n; ++i) w[i] -= c * q[i];
+      }
+    double b = 0.0;
+    for (int64_t i = 0; i < n; ++i) b += w[i] * w[i];
+    b = std::sqrt(b);
+    // extreme Ritz values by bisection on the Sturm count
+    double gl = 1e300, gh = -1e300;
+    for (size_t q = 0; q < al.size(); ++q) {
+      const double r = (q ? std::fabs(be[q - 1]) : 0.0) + (q < be.size() ? std::fabs(be[q]) : 0.0);
+      gl = std::min(gl, al[q] - r);
+      gh = std::max(gh, al[q] + r);
+    }
+    double a0 = gl, b0 = gh;
+    for (int it = 0; it < 200 && b0 - a0 > 1e-13 * (std::fabs(gl) + std::fabs(gh) + 1e-300); ++it) {
+      const double mid = 0.5 * (a0 + b0);
+      if (sturm_count(al, be, mid) >= 1) b0 = mid; else a0 = mid;
+    }
+    lo = 0.5 * (a0 + b0);
+    a0 = gl;
+    b0 = gh;
+    const int nn = (int)al.size();
+    for (int it = 0; it < 200 && b0 - a0 > 1e-13 * (std::fabs(gl) + std::fabs(gh) + 1e-300); ++it) {
+      const double mid = 0.5 * (a0 + b0);
+      if (sturm_count(al, be, mid) >= nn) b0 = mid; else a0 = mid;
+    }
+    hi = 0.5 * (a0 + b0);
+    const double range = std::max(hi - lo, 1e-300);
+    if (b < 1e-12 * range || j + 1 == mmax) break;   // invariant subspace or step limit
+    if (j >= 20 && std::fabs(hi - prev_hi) < 1e-10 * range && std::fabs(lo - prev_lo) < 1e-10 * range) break;
+    prev_hi = hi;
+    prev_lo = lo;
+    be.push_back(b);
+    for (int64_t i = 0; i < n; ++i) v[i] = w[i] / b;
+  }
+  return std::isfinite(lo) && std::isfinite(hi);
+}
+
+bool spectral_interval(const SystemSpec &s, double omega, double &Emin, double &Emax) {
+  double lo_sum = 0.0, hi_sum = 0.0;
+  int k0 = 0;
+  for (int rad = 0; rad < 2; ++rad) {
+    RadicalOp op;
+    op.n = rad == 0 ? s.N1 : s.N2;
+    op.omega = omega;
+    int64_t st = 1;
+    for (int q = 0; q < op.n; ++q) {
+      const int k = k0 + q;
+      op.stride.push_back(st);
+      op.d.push_back(s.two_I[k] + 1);
+      op.a.push_back(s.a[k]);
+      op.twoI.push_back(s.two_I[k]);
+      st *= s.two_I[k] + 1;
+    }
+    op.dim = 2 * st;
+    k0 += op.n;
+    double lo, hi;
+    if (!radical_extremes(op, lo, hi)) return false;
+    lo_sum += lo;
+    hi_sum += hi;
+  }
+  // 2 J S1.S2 has eigenvalues J/2 (triplet) and -3J/2 (singlet): Weyl's inequality.
+  Emax = hi_sum + std::max(0.5 * s.J, -1.5 * s.J);
+  Emin = lo_sum + std::min(0.5 * s.J, -1.5 * s.J);
+  return true;
+}
+
 // Gauss-Legendre nodes and weights on [-1, 1] (Newton iteration on P_n).
 static void gauss_legendre(int n, std::vector<double> &x, std::vector<double> &w) {
   x.assign(n, 0.0);
@@ -139,10 +276,21 @@ bool plan_field(const SystemSpec &s, double B_mT, double tol, double rdt, double
   out.B_mT = B_mT;
   out.omega = s.gamma * std::fabs(B_mT);
   const double dk = std::fabs(s.kS - s.kT);
-  out.rho = spectral_radius_bound(s, out.omega) * r_scale;
+  // Spectrum of H: per-radical Lanczos extremes (with a relative safety margin), else the
+  // triangle-inequality bound.
+  double Emin = 0.0, Emax = 0.0, centre = 0.0, half = spectral_radius_bound(s, out.omega);
+  if (spectral_interval(s, out.omega, Emin, Emax)) {
+    const double hw = 0.5 * (Emax - Emin);
+    const double margin = 0.01 * hw + 1e-9;
+    if (hw + margin < half) {
+      centre = 0.5 * (Emax + Emin);
+      half = hw + margin;
+    }
+  }
+  out.rho = half * r_scale;
   // r covers the real spectrum; keep it above dk/4 so the imaginary extent stays <= 1.
   out.r = std::max({out.rho, 0.25 * dk, 1e-9});
-  out.c_re = 0.0;
+  out.c_re = centre;
   out.c_im = -0.25 * dk;
   out.n_steps = std::max<int64_t>(1, (int64_t)std::ceil(out.r * s.T / rdt - 1e-12));
   out.dt = s.T / (double)out.n_steps;

@@ -66,4 +66,9 @@ bool plan_field(const SystemSpec &s, double B_mT, double tol, double rdt, double
 // with ||I.S|| = (I+1)/2 for a spin-1/2 electron and ||S1.S2|| = 3/4).
 double spectral_radius_bound(const SystemSpec &s, double omega);
 
+// [Emin, Emax] containing the spectrum of H: with J = 0 the spectrum of H is the sum of
+// the spectra of the two radical Hamiltonians (each found by Lanczos on its own 2 Z_i
+// dimensional space); J shifts eigenvalues by at most its extreme values J/2, -3J/2.
+bool spectral_interval(const SystemSpec &s, double omega, double &Emin, double &Emax);
+
 }  // namespace rp

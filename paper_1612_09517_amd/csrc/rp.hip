@@ -189,11 +189,11 @@ __global__ __launch_bounds__(256) void k_init(InitArgs<R> a) {
     const cx<double> c = t[k * (RP_MAX_TWO_I + 1) + n];
     p = {p.x * c.x - p.y * c.y, p.x * c.y + p.y * c.x};
   }
-  cx<R> *o = a.psi + (job * a.Z + M) * 4;
+  cx<R> *o = a.psi + job * a.Z * 4 + M;   // planes (aa, ab, ba, bb), each Z long
   o[0] = {R(0), R(0)};
-  o[1] = {R(p.x), R(p.y)};
-  o[2] = {R(-p.x), R(-p.y)};
-  o[3] = {R(0), R(0)};
+  o[a.Z] = {R(p.x), R(p.y)};
+  o[2 * a.Z] = {R(-p.x), R(-p.y)};
+  o[3 * a.Z] = {R(0), R(0)};
 }
 
 // ----------------------------------------------------------------------------- Chebyshev term
@@ -209,8 +209,188 @@ __device__ __forceinline__ void load2<float>(const cx<float> *p, cx<float> &a, c
   b = {v.z, v.w};
 }
 
-template <typename R, bool HALF, bool FIRST>
-__global__ __launch_bounds__(256) void k_cheb(TermArgs<R> ta, SysArgs<R> sa) {
+// Which step accumulator work a term launch does (see propagate_system).
+enum TermMode { kFirst = 0, kPlain = 1, kAcc3 = 2 };
+
+// Adds the flip-flop contribution of one spin-1/2 nucleus on radical 1 (r1) or 2, given
+// the two partner components it couples to (bit: this nucleus's digit at M).
+template <typename R>
+__device__ __forceinline__ void flip_half(bool r1, int bit, R f, cx<R> p0, cx<R> p1, cx<R> &y0, cx<R> &y1,
+                                          cx<R> &y2, cx<R> &y3) {
+  const cx<R> u0 = cscale(f, p0), u1 = cscale(f, p1), z = {R(0), R(0)};
+  if (r1) {   // bit 0: (aa, ab) of the partner feed (ba, bb); bit 1: (ba, bb) feed (aa, ab)
+    y0 = cadd(y0, csel(bit, u0, z));
+    y1 = cadd(y1, csel(bit, u1, z));
+    y2 = cadd(y2, csel(bit, z, u0));
+    y3 = cadd(y3, csel(bit, z, u1));
+  } else {    // bit 0: (aa, ba) feed (ab, bb); bit 1: (ab, bb) feed (aa, ba)
+    y0 = cadd(y0, csel(bit, u0, z));
+    y2 = cadd(y2, csel(bit, u1, z));
+    y1 = cadd(y1, csel(bit, z, u0));
+    y3 = cadd(y3, csel(bit, z, u1));
+  }
+}
+
+// Everything after H x: diagonal, exchange, i beta P_S, shift and scale, recurrence,
+// stores of phi_{n+1}, its singlet amplitude and the accumulator.
+template <typename R, int MODE>
+__device__ __forceinline__ void finish_term(const TermArgs<R> &ta, const SysArgs<R> &sa, const FieldDev<R> &fp,
+                                            int fi, int64_t job, int64_t M, R h1, R h2, cx<R> x0, cx<R> x1,
+                                            cx<R> x2, cx<R> x3, cx<R> o0, cx<R> o1, cx<R> o2, cx<R> o3,
+                                            cx<R> y0, cx<R> y1, cx<R> y2, cx<R> y3) {
+  // Diagonal: omega (s1 + s2) + s1 h1 + s2 h2 + 2 J s1 s2 with s = +-1/2.
+  const R hs = R(0.5) * (h1 + h2), hd = R(0.5) * (h1 - h2), hj = R(0.5) * sa.J;
+  y0 = cadd(y0, cscale(fp.omega + hs + hj, x0));
+  y1 = cadd(y1, cadd(cscale(hd - hj, x1), cscale(sa.J, x2)));
+  y2 = cadd(y2, cadd(cscale(-hd - hj, x2), cscale(sa.J, x1)));
+  y3 = cadd(y3, cscale(-fp.omega - hs + hj, x3));
+  // i beta P_S x: P_S acts on (ab, ba) as [[1,-1],[-1,1]]/2.
+  const cx<R> t = {R(0.5) * (x1.x - x2.x), R(0.5) * (x1.y - x2.y)};
+  const cx<R> ibt = {-sa.beta * t.y, sa.beta * t.x};
+  y1 = cadd(y1, ibt);
+  y2 = csub(y2, ibt);
+  const cx<R> c = {fp.c_re, fp.c_im};
+  const R s = MODE == kFirst ? fp.s1 : fp.s2;
+  cx<R> z0 = cscale(s, csub(y0, cmul(c, x0)));
+  cx<R> z1 = cscale(s, csub(y1, cmul(c, x1)));
+  cx<R> z2 = cscale(s, csub(y2, cmul(c, x2)));
+  cx<R> z3 = cscale(s, csub(y3, cmul(c, x3)));
+  if (MODE != kFirst) {
+    z0 = csub(z0, o0);
+    z1 = csub(z1, o1);
+    z2 = csub(z2, o2);
+    z3 = csub(z3, o3);
+  }
+  const int64_t Z = sa.Z;
+  const int64_t e = job * Z * 4 + M;
+  cx<R> *O = ta.phio + e;
+  O[0] = z0;
+  O[Z] = z1;
+  O[2 * Z] = z2;
+  O[3 * Z] = z3;
+  ta.dnext[job * sa.Z + M] = csub(z1, z2);
+  const cx<R> *cf = ta.coef + (int64_t)fi * ta.n_terms;
+  cx<R> *A = ta.acc + e;
+  if (MODE == kFirst) {
+    const cx<R> a0 = cf[0], a1 = cf[1];
+    A[0] = cadd(cmul(a0, x0), cmul(a1, z0));
+    A[Z] = cadd(cmul(a0, x1), cmul(a1, z1));
+    A[2 * Z] = cadd(cmul(a0, x2), cmul(a1, z2));
+    A[3 * Z] = cadd(cmul(a0, x3), cmul(a1, z3));
+    ta.dfirst[job * sa.Z + M] = csub(x1, x2);
+  } else if (MODE == kAcc3) {
+    // acc += a_{n-1} phi_{n-1} + a_n phi_n + a_{n+1} phi_{n+1}
+    const cx<R> am = cf[ta.n - 1], a0 = cf[ta.n], ap = cf[ta.n + 1];
+    const cx<R> v0 = A[0], v1 = A[Z], v2 = A[2 * Z], v3 = A[3 * Z];
+    A[0] = cadd(v0, cadd(cadd(cmul(am, o0), cmul(a0, x0)), cmul(ap, z0)));
+    A[Z] = cadd(v1, cadd(cadd(cmul(am, o1), cmul(a0, x1)), cmul(ap, z1)));
+    A[2 * Z] = cadd(v2, cadd(cadd(cmul(am, o2), cmul(a0, x2)), cmul(ap, z2)));
+    A[3 * Z] = cadd(v3, cadd(cadd(cmul(am, o3), cmul(a0, x3)), cmul(ap, z3)));
+  }
+}
+
+// One Chebyshev term for systems of spin-1/2 nuclei with strides 2^k.  The workgroup's
+// 256 nuclear indices form a tile that holds every partner along the fast axes
+// (stride < 256); the tile is staged in LDS and those partners are read from it.
+// Partners along the slow axes are read from global memory in batches of 8 loads.
+template <typename R, int MODE>
+__global__ __launch_bounds__(256) void k_cheb_half(TermArgs<R> ta, SysArgs<R> sa) {
+  __shared__ cx<R> tile[kBlock * 4];
+  __shared__ double lds[4];
+  const int64_t total = (int64_t)ta.njobs * ta.nbx;
+  const int64_t L = xcd_remap(blockIdx.x, total);
+  const int64_t job = L / ta.nbx, bx = L - job * ta.nbx;
+  const int tid = threadIdx.x;
+  const int64_t M = bx * kBlock + tid;
+  const bool live = M < sa.Z;
+  const int fi = ta.job_field[job];
+  const FieldDev<R> fp = ta.fields[fi];
+  const int64_t Z = sa.Z;
+  const cx<R> *X = ta.phin + job * Z * 4;
+  const cx<R> zero = {R(0), R(0)};
+  cx<R> x0 = zero, x1 = zero, x2 = zero, x3 = zero, o0 = zero, o1 = zero, o2 = zero, o3 = zero;
+  if (live) {
+    x0 = X[M];
+    x1 = X[Z + M];
+    x2 = X[2 * Z + M];
+    x3 = X[3 * Z + M];
+    if (MODE != kFirst) {
+      const cx<R> *O = ta.phio + job * Z * 4 + M;
+      o0 = O[0];
+      o1 = O[Z];
+      o2 = O[2 * Z];
+      o3 = O[3 * Z];
+    }
+  }
+  tile[tid] = x0;                 // planar tile: tile[e * 256 + t]
+  tile[kBlock + tid] = x1;
+  tile[2 * kBlock + tid] = x2;
+  tile[3 * kBlock + tid] = x3;
+  __syncthreads();
+  double nrm = 0.0;
+  if (live) {
+    cx<R> y0 = zero, y1 = zero, y2 = zero, y3 = zero;
+    R h1 = R(0), h2 = R(0);
+    const int kf = sa.N < 8 ? sa.N : 8;   // nuclei whose partners lie in the tile
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      if (k < kf) {
+        const int bit = (tid >> k) & 1;
+        const int pt = tid ^ (1 << k);
+        const bool r1 = k < sa.N1;
+        const R mk = bit ? R(-0.5) : R(0.5);
+        if (r1) h1 += sa.a[k] * mk; else h2 += sa.a[k] * mk;
+        cx<R> p0, p1;
+        if (r1) {
+          p0 = tile[(2 * bit) * kBlock + pt];
+          p1 = tile[(2 * bit + 1) * kBlock + pt];
+        } else {
+          p0 = tile[bit * kBlock + pt];
+          p1 = tile[(bit + 2) * kBlock + pt];
+        }
+        flip_half(r1, bit, sa.f[k][0], p0, p1, y0, y1, y2, y3);
+      }
+    }
+    for (int k0 = kf; k0 < sa.N; k0 += 8) {
+      cx<R> pa[8], pb[8];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const int k = k0 + j;
+        if (k < sa.N) {
+          const int bit = (int)((M >> k) & 1);
+          const int64_t P = M ^ ((int64_t)1 << k);
+          // slow axis: every lane of a wave has the same bit, so both loads are coalesced
+          const int c0 = k < sa.N1 ? 2 * bit : bit, c1 = k < sa.N1 ? 2 * bit + 1 : bit + 2;
+          pa[j] = X[c0 * Z + P];
+          pb[j] = X[c1 * Z + P];
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const int k = k0 + j;
+        if (k < sa.N) {
+          const int bit = (int)((M >> k) & 1);
+          const bool r1 = k < sa.N1;
+          const R mk = bit ? R(-0.5) : R(0.5);
+          if (r1) h1 += sa.a[k] * mk; else h2 += sa.a[k] * mk;
+          flip_half(r1, bit, sa.f[k][0], pa[j], pb[j], y0, y1, y2, y3);
+        }
+      }
+    }
+    finish_term<R, MODE>(ta, sa, fp, fi, job, M, h1, h2, x0, x1, x2, x3, o0, o1, o2, o3, y0, y1, y2, y3);
+    if (MODE == kFirst)
+      nrm = (double)x0.x * x0.x + (double)x0.y * x0.y + (double)x1.x * x1.x + (double)x1.y * x1.y +
+            (double)x2.x * x2.x + (double)x2.y * x2.y + (double)x3.x * x3.x + (double)x3.y * x3.y;
+  }
+  if (MODE == kFirst) {
+    const double t = block_sum(nrm, lds);
+    if (tid == 0) ta.part_norm[job * ta.nbx + bx] = t;
+  }
+}
+
+// One Chebyshev term for any mix of spins (mixed-radix digits, partners from global memory).
+template <typename R, int MODE>
+__global__ __launch_bounds__(256) void k_cheb_gen(TermArgs<R> ta, SysArgs<R> sa) {
   __shared__ double lds[4];
   const int64_t total = (int64_t)ta.njobs * ta.nbx;
   const int64_t L = xcd_remap(blockIdx.x, total);
@@ -221,130 +401,73 @@ __global__ __launch_bounds__(256) void k_cheb(TermArgs<R> ta, SysArgs<R> sa) {
   const FieldDev<R> fp = ta.fields[fi];
   double nrm = 0.0;
   if (live) {
-    const cx<R> *X = ta.phin + job * sa.Z * 4;
-    cx<R> x0, x1, x2, x3;
-    load2(X + 4 * M, x0, x1);
-    load2(X + 4 * M + 2, x2, x3);
-    cx<R> y0 = {R(0), R(0)}, y1 = y0, y2 = y0, y3 = y0;
+    const cx<R> zero = {R(0), R(0)};
+    const int64_t Z = sa.Z;
+    const cx<R> *X = ta.phin + job * Z * 4;
+    cx<R> o0 = zero, o1 = zero, o2 = zero, o3 = zero;
+    const cx<R> x0 = X[M], x1 = X[Z + M], x2 = X[2 * Z + M], x3 = X[3 * Z + M];
+    if (MODE != kFirst) {
+      const cx<R> *O = ta.phio + job * Z * 4 + M;
+      o0 = O[0];
+      o1 = O[Z];
+      o2 = O[2 * Z];
+      o3 = O[3 * Z];
+    }
+    cx<R> y0 = zero, y1 = zero, y2 = zero, y3 = zero;
     R h1 = R(0), h2 = R(0);
+    int64_t rem = M;
     for (int k = 0; k < sa.N; ++k) {
-      if (HALF) {
-        const int bit = (int)((M >> sa.shift[k]) & 1);
-        const int64_t P = M ^ (int64_t)sa.stride[k];
-        const R fk = sa.f[k][0];
-        const R mk = bit ? R(-0.5) : R(0.5);
-        if (k < sa.N1) {
-          h1 += sa.a[k] * mk;
-          cx<R> p0, p1;
-          load2(X + 4 * P + 2 * bit, p0, p1);   // bit 0: (aa, ab) -> (ba, bb); bit 1: (ba, bb) -> (aa, ab)
-          const cx<R> u0 = cscale(fk, p0), u1 = cscale(fk, p1);
-          y0 = cadd(y0, csel(bit, u0, cx<R>{R(0), R(0)}));
-          y1 = cadd(y1, csel(bit, u1, cx<R>{R(0), R(0)}));
-          y2 = cadd(y2, csel(bit, cx<R>{R(0), R(0)}, u0));
-          y3 = cadd(y3, csel(bit, cx<R>{R(0), R(0)}, u1));
+      const int64_t st = sa.stride[k];
+      const int dk = sa.d[k];
+      const int64_t q = rem / dk;
+      const int n = (int)(rem - q * dk);
+      rem = q;
+      const R mk = R(0.5) * R(dk - 1) - R(n);
+      const bool r1 = k < sa.N1;
+      if (r1) h1 += sa.a[k] * mk; else h2 += sa.a[k] * mk;
+      if (n > 0) {        // partner digit n-1: beta component -> alpha component (I- S+)
+        const R fk = sa.f[k][n - 1];
+        const cx<R> *Pp = X + (M - st);
+        if (r1) {
+          y0 = cadd(y0, cscale(fk, Pp[2 * Z]));
+          y1 = cadd(y1, cscale(fk, Pp[3 * Z]));
         } else {
-          h2 += sa.a[k] * mk;
-          const cx<R> p0 = X[4 * P + bit], p1 = X[4 * P + bit + 2];  // bit 0: (aa, ba); bit 1: (ab, bb)
-          const cx<R> u0 = cscale(fk, p0), u1 = cscale(fk, p1);
-          y0 = cadd(y0, csel(bit, u0, cx<R>{R(0), R(0)}));
-          y2 = cadd(y2, csel(bit, u1, cx<R>{R(0), R(0)}));
-          y1 = cadd(y1, csel(bit, cx<R>{R(0), R(0)}, u0));
-          y3 = cadd(y3, csel(bit, cx<R>{R(0), R(0)}, u1));
+          y0 = cadd(y0, cscale(fk, Pp[Z]));
+          y2 = cadd(y2, cscale(fk, Pp[3 * Z]));
         }
-      } else {
-        const int64_t st = sa.stride[k];
-        const int dk = sa.d[k];
-        const int n = (int)((M / st) % dk);
-        const R mk = R(0.5) * R(dk - 1) - R(n);
-        const bool r1 = k < sa.N1;
-        if (r1) h1 += sa.a[k] * mk; else h2 += sa.a[k] * mk;
-        if (n > 0) {        // partner digit n-1: beta component -> alpha component (I- S+)
-          const R fk = sa.f[k][n - 1];
-          const cx<R> *Pp = X + 4 * (M - st);
-          if (r1) {
-            y0 = cadd(y0, cscale(fk, Pp[2]));
-            y1 = cadd(y1, cscale(fk, Pp[3]));
-          } else {
-            y0 = cadd(y0, cscale(fk, Pp[1]));
-            y2 = cadd(y2, cscale(fk, Pp[3]));
-          }
-        }
-        if (n < dk - 1) {   // partner digit n+1: alpha component -> beta component (I+ S-)
-          const R fk = sa.f[k][n];
-          const cx<R> *Pp = X + 4 * (M + st);
-          if (r1) {
-            y2 = cadd(y2, cscale(fk, Pp[0]));
-            y3 = cadd(y3, cscale(fk, Pp[1]));
-          } else {
-            y1 = cadd(y1, cscale(fk, Pp[0]));
-            y3 = cadd(y3, cscale(fk, Pp[2]));
-          }
+      }
+      if (n < dk - 1) {   // partner digit n+1: alpha component -> beta component (I+ S-)
+        const R fk = sa.f[k][n];
+        const cx<R> *Pp = X + (M + st);
+        if (r1) {
+          y2 = cadd(y2, cscale(fk, Pp[0]));
+          y3 = cadd(y3, cscale(fk, Pp[Z]));
+        } else {
+          y1 = cadd(y1, cscale(fk, Pp[0]));
+          y3 = cadd(y3, cscale(fk, Pp[2 * Z]));
         }
       }
     }
-    // Diagonal: omega (s1 + s2) + s1 h1 + s2 h2 + 2 J s1 s2 with s = +-1/2.
-    const R hs = R(0.5) * (h1 + h2), hd = R(0.5) * (h1 - h2), hj = R(0.5) * sa.J;
-    y0 = cadd(y0, cscale(fp.omega + hs + hj, x0));
-    y1 = cadd(y1, cadd(cscale(hd - hj, x1), cscale(sa.J, x2)));
-    y2 = cadd(y2, cadd(cscale(-hd - hj, x2), cscale(sa.J, x1)));
-    y3 = cadd(y3, cscale(-fp.omega - hs + hj, x3));
-    // i beta P_S x: P_S acts on (ab, ba) as [[1,-1],[-1,1]]/2.
-    const cx<R> t = {R(0.5) * (x1.x - x2.x), R(0.5) * (x1.y - x2.y)};
-    const cx<R> ibt = {-sa.beta * t.y, sa.beta * t.x};
-    y1 = cadd(y1, ibt);
-    y2 = csub(y2, ibt);
-    // (y - c x) / r, doubled for the three-term recurrence.
-    const cx<R> c = {fp.c_re, fp.c_im};
-    const R s = FIRST ? fp.s1 : fp.s2;
-    cx<R> z0 = cscale(s, csub(y0, cmul(c, x0)));
-    cx<R> z1 = cscale(s, csub(y1, cmul(c, x1)));
-    cx<R> z2 = cscale(s, csub(y2, cmul(c, x2)));
-    cx<R> z3 = cscale(s, csub(y3, cmul(c, x3)));
-    cx<R> *O = ta.phio + (job * sa.Z + M) * 4;
-    if (!FIRST) {
-      cx<R> o0, o1, o2, o3;
-      load2(O, o0, o1);
-      load2(O + 2, o2, o3);
-      z0 = csub(z0, o0);
-      z1 = csub(z1, o1);
-      z2 = csub(z2, o2);
-      z3 = csub(z3, o3);
-    }
-    O[0] = z0;
-    O[1] = z1;
-    O[2] = z2;
-    O[3] = z3;
-    ta.dnext[job * sa.Z + M] = csub(z1, z2);
-    const cx<R> an = ta.coef[(int64_t)fi * ta.n_terms + ta.n + 1];
-    cx<R> *A = ta.acc + (job * sa.Z + M) * 4;
-    if (FIRST) {
-      const cx<R> a0 = ta.coef[(int64_t)fi * ta.n_terms];
-      A[0] = cadd(cmul(a0, x0), cmul(an, z0));
-      A[1] = cadd(cmul(a0, x1), cmul(an, z1));
-      A[2] = cadd(cmul(a0, x2), cmul(an, z2));
-      A[3] = cadd(cmul(a0, x3), cmul(an, z3));
-      ta.dfirst[job * sa.Z + M] = csub(x1, x2);
+    finish_term<R, MODE>(ta, sa, fp, fi, job, M, h1, h2, x0, x1, x2, x3, o0, o1, o2, o3, y0, y1, y2, y3);
+    if (MODE == kFirst)
       nrm = (double)x0.x * x0.x + (double)x0.y * x0.y + (double)x1.x * x1.x + (double)x1.y * x1.y +
             (double)x2.x * x2.x + (double)x2.y * x2.y + (double)x3.x * x3.x + (double)x3.y * x3.y;
-    } else {
-      cx<R> a0v, a1v, a2v, a3v;
-      load2(A, a0v, a1v);
-      load2(A + 2, a2v, a3v);
-      A[0] = cadd(a0v, cmul(an, z0));
-      A[1] = cadd(a1v, cmul(an, z1));
-      A[2] = cadd(a2v, cmul(an, z2));
-      A[3] = cadd(a3v, cmul(an, z3));
-    }
   }
-  if (FIRST) {
+  if (MODE == kFirst) {
     const double t = block_sum(nrm, lds);
     if (threadIdx.x == 0) ta.part_norm[job * ta.nbx + bx] = t;
   }
 }
 
 // ----------------------------------------------------------------------------- in-step quadrature
-// part[job][bx] = ( sum_M sum_r |sum_n ell_nr (-i)^n d_n(M)|^2 ,  sum_M |d_0(M)|^2 / 2 )
+// part[job][bx] = ( sum_M sum_r |sum_n ell_nr (-i)^n d_n(M)|^2 ,  sum_M |d_0(M)|^2 / 2 ).
+// The factor ell is the same for every thread of a workgroup (one job, one field), so it
+// is read through the scalar cache into SGPRs and used as the uniform FMA operand; each
+// slab of singlet amplitudes is read once per pass of RC columns.
 template <typename R>
+using const_ptr = const __attribute__((address_space(4))) R *;
+
+template <typename R, int RC>
 __global__ __launch_bounds__(256) void k_quad(QuadArgs<R> qa) {
   __shared__ double lds[4];
   const int64_t total = (int64_t)qa.njobs * qa.nbx;
@@ -352,17 +475,19 @@ __global__ __launch_bounds__(256) void k_quad(QuadArgs<R> qa) {
   const int64_t job = L / qa.nbx, bx = L - job * qa.nbx;
   const int64_t M = bx * kBlock + threadIdx.x;
   const bool live = M < qa.Z;
-  const int fi = qa.job_field[job];
-  const R *ell = qa.ell + (int64_t)fi * qa.n_terms * qa.rank_pad;
+  const int fi = __builtin_amdgcn_readfirstlane(qa.job_field[job]);
+  const_ptr<R> ell = (const_ptr<R>)(qa.ell + (int64_t)fi * qa.n_terms * qa.rank_pad);
+  const cx<R> *dp = qa.d + job * qa.Z + (live ? M : 0);
   double acc = 0.0, ps = 0.0;
   if (live) {
-    const cx<R> *dp = qa.d + job * qa.Z + M;
-    for (int r0 = 0; r0 < qa.rank_pad; r0 += kQuadChunk) {
-      cx<R> W[kQuadChunk];
+    for (int r0 = 0; r0 < qa.rank_pad; r0 += RC) {
+      cx<R> W[RC];
 #pragma unroll
-      for (int r = 0; r < kQuadChunk; ++r) W[r] = {R(0), R(0)};
+      for (int r = 0; r < RC; ++r) W[r] = {R(0), R(0)};
+      cx<R> vn = dp[0];
       for (int n = 0; n < qa.n_terms; ++n) {
-        const cx<R> v = dp[(int64_t)n * qa.slab];
+        const cx<R> v = vn;
+        if (n + 1 < qa.n_terms) vn = dp[(int64_t)(n + 1) * qa.slab];
         cx<R> u;
         switch (n & 3) {          // multiply by (-i)^n
           case 0: u = v; break;
@@ -370,15 +495,18 @@ __global__ __launch_bounds__(256) void k_quad(QuadArgs<R> qa) {
           case 2: u = {-v.x, -v.y}; break;
           default: u = {-v.y, v.x}; break;
         }
-        const R *e = ell + (int64_t)n * qa.rank_pad + r0;
+        const_ptr<R> e = ell + (int64_t)n * qa.rank_pad + r0;
 #pragma unroll
-        for (int r = 0; r < kQuadChunk; ++r) {
-          W[r].x += e[r] * u.x;
-          W[r].y += e[r] * u.y;
+        for (int r = 0; r < RC; ++r) {
+          const R l = e[r];
+          W[r].x += l * u.x;
+          W[r].y += l * u.y;
         }
       }
+      R part = R(0);   // RC squares in the working precision, then accumulated in FP64
 #pragma unroll
-      for (int r = 0; r < kQuadChunk; ++r) acc += (double)W[r].x * W[r].x + (double)W[r].y * W[r].y;
+      for (int r = 0; r < RC; ++r) part += W[r].x * W[r].x + W[r].y * W[r].y;
+      acc += (double)part;
     }
     const cx<R> v0 = dp[0];
     ps = 0.5 * ((double)v0.x * v0.x + (double)v0.y * v0.y);
@@ -388,6 +516,20 @@ __global__ __launch_bounds__(256) void k_quad(QuadArgs<R> qa) {
   if (threadIdx.x == 0) {
     qa.part[(job * qa.nbx + bx) * 2] = s0;
     qa.part[(job * qa.nbx + bx) * 2 + 1] = s1;
+  }
+}
+
+template <typename R>
+static void launch_quad(int rcw, unsigned grid, hipStream_t st, const QuadArgs<R> &qa) {
+  switch (rcw) {
+    case 64: hipLaunchKernelGGL((k_quad<R, 64>), dim3(grid), dim3(kBlock), 0, st, qa); break;
+    case 56: hipLaunchKernelGGL((k_quad<R, 56>), dim3(grid), dim3(kBlock), 0, st, qa); break;
+    case 48: hipLaunchKernelGGL((k_quad<R, 48>), dim3(grid), dim3(kBlock), 0, st, qa); break;
+    case 40: hipLaunchKernelGGL((k_quad<R, 40>), dim3(grid), dim3(kBlock), 0, st, qa); break;
+    case 32: hipLaunchKernelGGL((k_quad<R, 32>), dim3(grid), dim3(kBlock), 0, st, qa); break;
+    case 24: hipLaunchKernelGGL((k_quad<R, 24>), dim3(grid), dim3(kBlock), 0, st, qa); break;
+    case 16: hipLaunchKernelGGL((k_quad<R, 16>), dim3(grid), dim3(kBlock), 0, st, qa); break;
+    default: hipLaunchKernelGGL((k_quad<R, 8>), dim3(grid), dim3(kBlock), 0, st, qa); break;
   }
 }
 
@@ -486,7 +628,7 @@ static int validate_system(const rp_system *s) {
 }
 
 struct Profile {
-  double term_ms = 0, term_launches = 0, elems = 0, bytes_per_elem = 0, quad_ms = 0, quad_launches = 0,
+  double term_ms = 0, term_launches = 0, elems = 0, bytes = 0, quad_ms = 0, quad_launches = 0,
          total_ms = 0, terms = 0;
 };
 static thread_local Profile g_prof;
@@ -618,7 +760,18 @@ static int propagate_system(const SystemSpec &spec, const double *B, int nB, con
     nt = std::max(nt, p.n_terms);
     rk = std::max(rk, p.rank);
   }
-  const int rkp = (rk + kQuadChunk - 1) / kQuadChunk * kQuadChunk;
+  // Pad the term count so that (nt - 2) is a multiple of 3: the accumulator is updated
+  // by the first launch (terms 0, 1) and then by every third launch (three terms each).
+  while ((nt - 2) % 3 != 0) ++nt;
+  // Quadrature rank padded to a multiple of 8; k_quad makes passes of rcw <= 64 (FP32) or
+  // 32 (FP64) columns, the widest multiple of 8 that divides the padded rank.
+  const int rkp = (rk + 7) / 8 * 8;
+  int rcw = 8;
+  for (int c = (sizeof(R) == 4 ? 64 : 32); c >= 8; c -= 8)
+    if (rkp % c == 0) {
+      rcw = c;
+      break;
+    }
   std::vector<FieldDev<R>> fdev(nB);
   std::vector<cx<R>> coef((size_t)nB * nt, cx<R>{R(0), R(0)});
   std::vector<R> ell((size_t)nB * nt * rkp, R(0));
@@ -662,6 +815,12 @@ static int propagate_system(const SystemSpec &spec, const double *B, int nB, con
   }
   int64_t chunk = std::min<int64_t>(total_jobs, budget / per_job);
   if (chunk < 1) return fail(RP_ENOMEM, "workspace too small for one wavepacket");
+  if (op.workspace <= 0) {
+    // Default chunk: the three wavepacket buffers of the chunk (about 192 MB) stay resident in
+    // the 256 MB Infinity Cache across launches, but every launch keeps at least 64 jobs.
+    const int64_t resident = std::max<int64_t>(64, ((int64_t)192 << 20) / (3 * vec_bytes));
+    chunk = std::min(chunk, resident);
+  }
   chunk = std::min<int64_t>(chunk, (((int64_t)1) << 24) / nbx);   // grid of < 2^24 workgroups
 
   // Device allocations.
@@ -783,27 +942,40 @@ static int propagate_system(const SystemSpec &spec, const double *B, int nB, con
       ta.n = 0;
       ta.dnext = D + slab;
       ta.dfirst = D;
+      const double eb = (double)sizeof(R) / 4.0;   // bytes per element, in units of complex-FP32 bytes
       log.mark(st);
       if (sa.all_half)
-        hipLaunchKernelGGL((k_cheb<R, true, true>), dim3(grid), dim3(kBlock), 0, st, ta, sa);
+        hipLaunchKernelGGL((k_cheb_half<R, kFirst>), dim3(grid), dim3(kBlock), 0, st, ta, sa);
       else
-        hipLaunchKernelGGL((k_cheb<R, false, true>), dim3(grid), dim3(kBlock), 0, st, ta, sa);
+        hipLaunchKernelGGL((k_cheb_gen<R, kFirst>), dim3(grid), dim3(kBlock), 0, st, ta, sa);
+      double bytes = 28.0 * eb;
       for (int n = 1; n + 1 < nt; ++n) {
-        // phi_{n+1} = 2 Gh phi_n - phi_{n-1}, written over phi_{n-1}
+        // phi_{n+1} = 2 Gh phi_n - phi_{n-1}, written over phi_{n-1}; every third launch also adds
+        // phi_{n-1}, phi_n, phi_{n+1} to the step accumulator.
         ta.phin = (n & 1) ? odd : even;
         ta.phio = (n & 1) ? even : odd;
         ta.n = n;
         ta.dnext = D + (int64_t)(n + 1) * slab;
-        if (sa.all_half)
-          hipLaunchKernelGGL((k_cheb<R, true, false>), dim3(grid), dim3(kBlock), 0, st, ta, sa);
-        else
-          hipLaunchKernelGGL((k_cheb<R, false, false>), dim3(grid), dim3(kBlock), 0, st, ta, sa);
+        const bool acc3 = (n % 3) == 0;
+        if (sa.all_half) {
+          if (acc3)
+            hipLaunchKernelGGL((k_cheb_half<R, kAcc3>), dim3(grid), dim3(kBlock), 0, st, ta, sa);
+          else
+            hipLaunchKernelGGL((k_cheb_half<R, kPlain>), dim3(grid), dim3(kBlock), 0, st, ta, sa);
+        } else {
+          if (acc3)
+            hipLaunchKernelGGL((k_cheb_gen<R, kAcc3>), dim3(grid), dim3(kBlock), 0, st, ta, sa);
+          else
+            hipLaunchKernelGGL((k_cheb_gen<R, kPlain>), dim3(grid), dim3(kBlock), 0, st, ta, sa);
+        }
+        bytes += (acc3 ? 42.0 : 26.0) * eb;
       }
       log.mark(st);
       log.close(0);
       if (log.on) {
         g_prof.term_launches += nt - 1;
         g_prof.elems += (double)(nt - 1) * (double)active * 4.0 * (double)Z;
+        g_prof.bytes += bytes * (double)active * 4.0 * (double)Z;
         g_prof.quad_launches += 1;
         g_prof.terms = nt;
       }
@@ -821,7 +993,7 @@ static int propagate_system(const SystemSpec &spec, const double *B, int nB, con
       qa.n_terms = nt;
       qa.rank_pad = rkp;
       log.mark(st);
-      hipLaunchKernelGGL(k_quad<R>, dim3(grid), dim3(kBlock), 0, st, qa);
+      launch_quad<R>(rcw, grid, st, qa);
       log.mark(st);
       log.close(1);
       FinArgs fa;
@@ -960,10 +1132,7 @@ extern "C" int rp_propagate(const rp_system *sys, int32_t n_sys, const double *B
   hipStream_t st = (hipStream_t)hip_stream;
   EventLog log;
   log.on = (op.flags & RP_FLAG_PROFILE) != 0;
-  if (log.on) {
-    g_prof = Profile();
-    g_prof.bytes_per_elem = op.precision == 64 ? 84.0 : 42.0;
-  }
+  if (log.on) g_prof = Profile();
   hipEvent_t t0 = log.mark(st);
   int64_t aoff = 0;
   for (int i = 0; i < n_sys; ++i) {
@@ -999,7 +1168,8 @@ extern "C" int rp_propagate(const rp_system *sys, int32_t n_sys, const double *B
 
 extern "C" int rp_profile_last(double *out, int32_t n) {
   if (!out || n < 0) return fail(RP_EINVAL, "bad profile buffer");
-  const double v[8] = {g_prof.term_ms, g_prof.term_launches, g_prof.elems, g_prof.bytes_per_elem,
+  const double v[8] = {g_prof.term_ms, g_prof.term_launches, g_prof.elems,
+                       g_prof.elems > 0 ? g_prof.bytes / g_prof.elems : 0.0,
                        g_prof.quad_ms, g_prof.quad_launches, g_prof.total_ms, g_prof.terms};
   const int m = n < 8 ? n : 8;
   for (int i = 0; i < m; ++i) out[i] = v[i];

@@ -53,10 +53,22 @@ def test_plan_coefficients_are_bessel_series():
     n = np.arange(p["n_terms"])
     want = np.where(n == 0, 1.0, 2.0) * (-1j) ** n * ss.jv(n, p["x"]) * np.exp(-1j * p["c"] * p["dt"])
     assert np.max(np.abs(p["coef"] - want)) < 1e-14
-    assert abs(p["c"] - (-0.25j * 1.5)) < 1e-15
+    assert abs(p["c"].imag - (-0.25 * 1.5)) < 1e-15
     assert abs(p["n_steps"] * p["dt"] - s.T_us) < 1e-12
     assert abs(p["x"] - p["r"] * p["dt"]) < 1e-12
     assert p["x"] <= 80.0 + 1e-9
+
+
+@pytest.mark.parametrize("two_I,J,B", [([1, 1, 1], 0.0, 0.0), ([1, 2, 1], 0.7, 2.5), ([2, 1, 3], -0.4, 6.0)])
+def test_plan_spectral_interval_contains_spectrum(two_I, J, B):
+    """[c - r, c + r] contains every eigenvalue of H (dense eigvalsh) and is tight."""
+    s = _sys(two_I=two_I, J_mT=J, a_mT=[0.8, -0.3, 0.5])
+    d = spin.DenseSystem((s.n1, s.n2), s.two_I, s.a_mT, J_mT=J)
+    ev = np.linalg.eigvalsh(d.H(B))
+    p = rp.plan_field(s, B)
+    c, r = p["c"].real, p["r"]
+    assert c - r <= ev.min() and ev.max() <= c + r
+    assert r <= 1.02 * (0.5 * (ev.max() - ev.min())) + 1.5 * abs(J) * s.gamma + 1e-9
 
 
 def test_plan_quadrature_factor():
