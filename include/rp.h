@@ -132,11 +132,50 @@ int rp_propagate(const rp_system *sys, int32_t n_sys, const double *B_mT, int32_
  *   cv_g      device [nB][M] control-variate values g, or NULL for the plain mean
  *   cv_mu     device [nB] known means of g (ignored when cv_g is NULL)
  *   cv_beta   device [nB] coefficients (ignored when cv_g is NULL); the estimate is
- *             mean(phi - beta (g - mu)), unbiased when mu = E[g] and beta is fixed
+ *             mean(phi - beta (g - mu)), unbiased when E[mu] = E[g] and beta is fixed
+ *             independently of the M samples
+ *   cv_mu_err device [nB] standard error of mu (mu taken from independent samples), or NULL
+ *             for 0; (beta cv_mu_err)^2 is added to stderr^2
  *   mean, stderr_  device [nB] outputs
  */
 int rp_yield(const double *phi, int32_t nB, int64_t M, const double *cv_g, const double *cv_mu,
-             const double *cv_beta, double *mean, double *stderr_, void *hip_stream);
+             const double *cv_beta, const double *cv_mu_err, double *mean, double *stderr_,
+             void *hip_stream);
+
+/*
+ * Learned control variate (for the Monte Carlo mean of Eq. 18).  A network g(Omega, B)
+ * with features x = (n(Omega_1), ..., n(Omega_N), log(B/mT + 0.05)) (unit vectors of Eq. 16),
+ * `depth` hidden layers of `width` units with exact-erf GELU, and a scalar output, is trained
+ * by mean-squared error on yields phi_S produced by rp_propagate.  Hidden-layer products run
+ * on MFMA with BF16 inputs and FP32 accumulation; parameters, Adam moments and gradients are
+ * FP32.  For callers who cannot guess the padded input width: n_in_pad = 16 * ceil(n_in / 16).
+ *
+ * Packed parameter layout (FP32, device): for each hidden layer l, W_l [fan_in][width]
+ * (fan_in = n_in_pad for l = 0, else width) then b_l [width]; then the output weights
+ * w [width] and the output bias (1 value).
+ *
+ * rp_mlp_param_count     number of packed parameters (-1 for a bad shape: width must be a
+ *                        positive multiple of 16, 1 <= depth <= 8).
+ * rp_mlp_workspace_floats  FP32 workspace needed by forward/train calls on `rows` rows.
+ * rp_mlp_features        x[row][0 .. n_in_pad) (device) for every field b and sample s, from a
+ *                        device [M][N][2] angle array and device fields B_mT [nB]; row = b*M + s,
+ *                        or s*nB + b when sample_major != 0 (training batches then mix fields).
+ * rp_mlp_forward         y[rows] = g(x) (device).
+ * rp_mlp_train_step      one Adam step (beta1 0.9, beta2 0.999, eps 1e-8; step >= 1 is the
+ *                        Adam time step) on the batch (x, target); optional device outputs:
+ *                        grad_out [param_count] (the gradient of the mean squared error) and
+ *                        sq_err [rows] (squared errors before the update).  lr = 0 computes
+ *                        gradients without updating.
+ */
+int64_t rp_mlp_param_count(int32_t n_in, int32_t width, int32_t depth);
+int64_t rp_mlp_workspace_floats(int32_t n_in, int32_t width, int32_t depth, int64_t rows);
+int rp_mlp_features(const double *angles, int64_t M, int32_t N, const double *B_mT, int32_t nB,
+                    int32_t n_in_pad, int32_t sample_major, float *x, void *hip_stream);
+int rp_mlp_forward(int32_t n_in, int32_t width, int32_t depth, const float *params, const float *x,
+                   int64_t rows, float *y, float *workspace, void *hip_stream);
+int rp_mlp_train_step(int32_t n_in, int32_t width, int32_t depth, float *params, float *adam_m,
+                      float *adam_v, int64_t step, const float *x, const float *target, int64_t rows,
+                      float lr, float *grad_out, float *sq_err, float *workspace, void *hip_stream);
 
 /*
  * rp_profile_last -- timing of the most recent rp_propagate call on the calling
@@ -154,6 +193,13 @@ int rp_yield(const double *phi, int32_t nB, int64_t M, const double *cv_g, const
  * Returns the number of values written.
  */
 int rp_profile_last(double *out, int32_t n);
+
+/*
+ * rp_cv_beta -- per-field control-variate coefficient beta_b = Cov(phi, g) / Var(g) over the
+ * M samples (the variance-minimising coefficient), from device phi, g [nB][M] to device
+ * beta [nB] (0 where Var(g) = 0).  Take it from samples independent of the evaluation set.
+ */
+int rp_cv_beta(const double *phi, const double *g, int32_t nB, int64_t M, double *beta, void *hip_stream);
 
 /* Static text for a return code. */
 const char *rp_strerror(int code);

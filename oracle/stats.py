@@ -17,7 +17,7 @@ def mc_mean_error(phi):
     return mean, s / np.sqrt(M)
 
 
-def cv_mean_error(phi, g, mu, beta):
+def cv_mean_error(phi, g, mu, beta, mu_err=None):
     """Control-variate estimate mean(phi - beta (g - mu)) and its standard error.
 
     With beta and mu fixed independently of the evaluation samples the
@@ -28,4 +28,7 @@ def cv_mean_error(phi, g, mu, beta):
     g = np.asarray(g, float)
     mu = np.asarray(mu, float)[..., None]
     beta = np.asarray(beta, float)[..., None]
-    return mc_mean_error(phi - beta * (g - mu))
+    m, e = mc_mean_error(phi - beta * (g - mu))
+    if mu_err is not None:
+        e = np.sqrt(e * e + (beta[..., 0] * np.asarray(mu_err, float)) ** 2)
+    return m, e

@@ -563,7 +563,7 @@ __global__ __launch_bounds__(256) void k_scatter(const double *src, const int64_
 
 // ----------------------------------------------------------------------------- statistics (Eq. 23)
 struct StatArgs {
-  const double *phi, *g, *mu, *beta;
+  const double *phi, *g, *mu, *beta, *mu_err;
   double *mean, *err;
   int64_t M;
 };
@@ -589,8 +589,41 @@ __global__ __launch_bounds__(256) void k_stats(StatArgs a) {
   const double qt = block_sum(q, lds);
   if (threadIdx.x == 0) {
     a.mean[b] = m;
-    a.err[b] = a.M > 1 ? sqrt(qt / (double)(a.M - 1) / (double)a.M) : 0.0;
+    const double e2 = a.M > 1 ? qt / (double)(a.M - 1) / (double)a.M : 0.0;
+    a.err[b] = sqrt(e2 + (a.g && a.mu_err ? be * be * a.mu_err[b] * a.mu_err[b] : 0.0));
   }
+}
+
+// Per-field beta = Cov(phi, g) / Var(g) (two passes: means, then centred sums).
+struct BetaArgs {
+  const double *phi, *g;
+  double *beta;
+  int64_t M;
+};
+
+__global__ __launch_bounds__(256) void k_beta(BetaArgs a) {
+  __shared__ double lds[4];
+  __shared__ double means[2];
+  const double *p = a.phi + (int64_t)blockIdx.x * a.M, *g = a.g + (int64_t)blockIdx.x * a.M;
+  double sp = 0.0, sg = 0.0;
+  for (int64_t i = threadIdx.x; i < a.M; i += blockDim.x) {
+    sp += p[i];
+    sg += g[i];
+  }
+  const double tp = block_sum(sp, lds), tg = block_sum(sg, lds);
+  if (threadIdx.x == 0) {
+    means[0] = tp / (double)a.M;
+    means[1] = tg / (double)a.M;
+  }
+  __syncthreads();
+  double c = 0.0, v = 0.0;
+  for (int64_t i = threadIdx.x; i < a.M; i += blockDim.x) {
+    const double dp = p[i] - means[0], dg = g[i] - means[1];
+    c += dp * dg;
+    v += dg * dg;
+  }
+  const double tc = block_sum(c, lds), tv = block_sum(v, lds);
+  if (threadIdx.x == 0) a.beta[blockIdx.x] = tv > 0.0 ? tc / tv : 0.0;
 }
 
 // ============================================================================= host side
@@ -600,6 +633,8 @@ static int fail(int code, const std::string &m) {
   g_err = m;
   return code;
 }
+
+int mlp_fail(int code, const char *msg) { return fail(code, msg); }
 
 #define HIPCHK(call)                                                                   \
   do {                                                                                 \
@@ -1176,14 +1211,26 @@ extern "C" int rp_profile_last(double *out, int32_t n) {
   return m;
 }
 
+extern "C" int rp_cv_beta(const double *phi, const double *g, int32_t nB, int64_t M, double *beta,
+                          void *hip_stream) {
+  if (nB < 0 || M < 1) return fail(RP_EINVAL, "bad sizes");
+  if (nB == 0) return RP_OK;
+  if (!phi || !g || !beta) return fail(RP_EINVAL, "null pointer");
+  BetaArgs a{phi, g, beta, M};
+  hipLaunchKernelGGL(k_beta, dim3(nB), dim3(256), 0, (hipStream_t)hip_stream, a);
+  HIPCHK(hipGetLastError());
+  return RP_OK;
+}
+
 extern "C" int rp_yield(const double *phi, int32_t nB, int64_t M, const double *cv_g, const double *cv_mu,
-                        const double *cv_beta, double *mean, double *stderr_, void *hip_stream) {
+                        const double *cv_beta, const double *cv_mu_err, double *mean, double *stderr_,
+                        void *hip_stream) {
   if (nB < 0 || M < 0) return fail(RP_EINVAL, "negative count");
   if (nB == 0) return RP_OK;
   if (M == 0) return fail(RP_EINVAL, "M must be >= 1");
   if (!phi || !mean || !stderr_) return fail(RP_EINVAL, "null pointer");
   if (cv_g && (!cv_mu || !cv_beta)) return fail(RP_EINVAL, "control variate needs mu and beta");
-  StatArgs a{phi, cv_g, cv_mu, cv_beta, mean, stderr_, M};
+  StatArgs a{phi, cv_g, cv_mu, cv_beta, cv_mu_err, mean, stderr_, M};
   hipLaunchKernelGGL(k_stats, dim3(nB), dim3(256), 0, (hipStream_t)hip_stream, a);
   HIPCHK(hipGetLastError());
   return RP_OK;

@@ -38,7 +38,8 @@ class _Opts(ctypes.Structure):
 _lib = None
 
 EXPORTS = ["rp_sample", "rp_propagate", "rp_yield", "rp_strerror", "rp_last_error", "rp_bessel_j",
-           "rp_plan_field", "rp_profile_last"]
+           "rp_plan_field", "rp_profile_last", "rp_mlp_param_count", "rp_mlp_workspace_floats",
+           "rp_mlp_features", "rp_mlp_forward", "rp_mlp_train_step", "rp_cv_beta"]
 RP_FLAG_PROFILE = 1
 
 
@@ -55,14 +56,24 @@ def lib():
         op = ctypes.POINTER(_Opts)
         L.rp_sample.argtypes = [sp, u64, u32, u64, i64, i32, vp, vp]
         L.rp_propagate.argtypes = [sp, i32, dp, i32, vp, i64, op, vp, vp, vp]
-        L.rp_yield.argtypes = [vp, i32, i64, vp, vp, vp, vp, vp, vp]
+        L.rp_yield.argtypes = [vp, i32, i64, vp, vp, vp, vp, vp, vp, vp]
+        L.rp_mlp_param_count.argtypes = [i32, i32, i32]
+        L.rp_mlp_param_count.restype = i64
+        L.rp_mlp_workspace_floats.argtypes = [i32, i32, i32, i64]
+        L.rp_mlp_workspace_floats.restype = i64
+        L.rp_mlp_features.argtypes = [vp, i64, i32, vp, i32, i32, i32, vp, vp]
+        L.rp_cv_beta.argtypes = [vp, vp, i32, i64, vp, vp]
+        L.rp_mlp_forward.argtypes = [i32, i32, i32, vp, vp, i64, vp, vp, vp]
+        L.rp_mlp_train_step.argtypes = [i32, i32, i32, vp, vp, vp, i64, vp, vp, i64, ctypes.c_float, vp, vp,
+                                        vp, vp]
         L.rp_strerror.argtypes = [ctypes.c_int]
         L.rp_strerror.restype = ctypes.c_char_p
         L.rp_last_error.restype = ctypes.c_char_p
         L.rp_bessel_j.argtypes = [ctypes.c_double, i32, dp]
         L.rp_plan_field.argtypes = [sp, ctypes.c_double, op, dp, dp, dp]
         L.rp_profile_last.argtypes = [dp, i32]
-        for f in ("rp_sample", "rp_propagate", "rp_yield", "rp_bessel_j", "rp_plan_field", "rp_profile_last"):
+        for f in ("rp_sample", "rp_propagate", "rp_yield", "rp_bessel_j", "rp_plan_field", "rp_profile_last",
+                  "rp_mlp_features", "rp_mlp_forward", "rp_mlp_train_step", "rp_cv_beta"):
             getattr(L, f).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -145,7 +156,7 @@ def propagate(systems, B_mT, angles, M, precision=64, init_mode=0, tol=0.0, rdt=
     return out
 
 
-def yield_stats(phi, cv_g=None, cv_mu=None, cv_beta=None):
+def yield_stats(phi, cv_g=None, cv_mu=None, cv_beta=None, cv_mu_err=None):
     """rp_yield: per-field mean and standard error of phi [nB][M] (CUDA float64)."""
     import torch
     phi = phi.reshape(-1, phi.shape[-1]).contiguous()
@@ -155,9 +166,75 @@ def yield_stats(phi, cv_g=None, cv_mu=None, cv_beta=None):
     g = _dev_ptr(cv_g.reshape(nB, M).contiguous(), torch.float64) if cv_g is not None else None
     mu = _dev_ptr(cv_mu.contiguous(), torch.float64) if cv_mu is not None else None
     be = _dev_ptr(cv_beta.contiguous(), torch.float64) if cv_beta is not None else None
-    _check(lib().rp_yield(_dev_ptr(phi, torch.float64), nB, M, g, mu, be, _dev_ptr(mean, torch.float64),
+    mv = _dev_ptr(cv_mu_err.contiguous(), torch.float64) if cv_mu_err is not None else None
+    _check(lib().rp_yield(_dev_ptr(phi, torch.float64), nB, M, g, mu, be, mv, _dev_ptr(mean, torch.float64),
                           _dev_ptr(err, torch.float64), _stream(torch)))
     return mean, err
+
+
+# ----------------------------------------------------------------------------- control-variate network
+def mlp_param_count(n_in, width=256, depth=3):
+    n = lib().rp_mlp_param_count(n_in, width, depth)
+    if n < 0:
+        raise ValueError("bad network shape")
+    return n
+
+
+def mlp_in_pad(n_in):
+    return (n_in + 15) // 16 * 16
+
+
+def mlp_workspace(n_in, width, depth, rows):
+    import torch
+    n = lib().rp_mlp_workspace_floats(n_in, width, depth, rows)
+    return torch.empty(max(n, 1), dtype=torch.float32, device="cuda")
+
+
+def mlp_features(angles, B_mT, n_in, sample_major=False):
+    """rp_mlp_features: [nB*M][n_in_pad] float32 features (field-major rows unless sample_major)."""
+    import torch
+    M, N = angles.shape[0], angles.shape[1]
+    B = torch.as_tensor(np.asarray(B_mT, np.float64).reshape(-1), device="cuda")
+    nB = B.numel()
+    x = torch.empty((nB * M, mlp_in_pad(n_in)), dtype=torch.float32, device="cuda")
+    _check(lib().rp_mlp_features(_dev_ptr(angles.contiguous(), torch.float64), M, N, _dev_ptr(B, torch.float64),
+                                 nB, x.shape[1], 1 if sample_major else 0, _dev_ptr(x, torch.float32),
+                                 _stream(torch)))
+    return x
+
+
+def cv_beta(phi, g):
+    """rp_cv_beta: per-field Cov(phi, g)/Var(g) for device float64 [nB][M] arrays."""
+    import torch
+    phi = phi.contiguous()
+    g = g.contiguous()
+    nB, M = phi.shape
+    beta = torch.empty(nB, dtype=torch.float64, device="cuda")
+    _check(lib().rp_cv_beta(_dev_ptr(phi, torch.float64), _dev_ptr(g, torch.float64), nB, M,
+                            _dev_ptr(beta, torch.float64), _stream(torch)))
+    return beta
+
+
+def mlp_forward(params, x, n_in, width=256, depth=3, workspace=None):
+    import torch
+    rows = x.shape[0]
+    y = torch.empty(rows, dtype=torch.float32, device="cuda")
+    ws = workspace if workspace is not None else mlp_workspace(n_in, width, depth, rows)
+    _check(lib().rp_mlp_forward(n_in, width, depth, _dev_ptr(params, torch.float32), _dev_ptr(x, torch.float32),
+                                rows, _dev_ptr(y, torch.float32), _dev_ptr(ws, torch.float32), _stream(torch)))
+    return y
+
+
+def mlp_train_step(params, adam_m, adam_v, step, x, target, n_in, width=256, depth=3, lr=1e-3,
+                   grad_out=None, sq_err=None, workspace=None):
+    import torch
+    rows = x.shape[0]
+    ws = workspace if workspace is not None else mlp_workspace(n_in, width, depth, rows)
+    _check(lib().rp_mlp_train_step(n_in, width, depth, _dev_ptr(params, torch.float32),
+                                   _dev_ptr(adam_m, torch.float32), _dev_ptr(adam_v, torch.float32), step,
+                                   _dev_ptr(x, torch.float32), _dev_ptr(target, torch.float32), rows,
+                                   float(lr), _dev_ptr(grad_out, torch.float32), _dev_ptr(sq_err, torch.float32),
+                                   _dev_ptr(ws, torch.float32), _stream(torch)))
 
 
 def profile_last():

@@ -1,0 +1,141 @@
+"""GPU checks of the control-variate network and estimator against the FP64 oracle.
+
+Tolerances for the network: every hidden-layer product rounds its inputs to BF16
+(relative rounding error <= 2^-9 per input), so layer outputs carry relative errors of a
+few 1e-3; after three hidden layers we require a relative L2 error below 3e-2 for outputs
+and 5e-2 for gradients.  Elementwise FP32 steps (features, Adam) are checked at 1e-6."""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import coherent, mlp, philox, spin, stats, yields
+from paper_1612_09517_amd import cv, rp
+from paper_1612_09517_amd.workloads import SpinSystem
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _device():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    rp.lib()
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _t(x, dt=torch.float32):
+    return torch.tensor(np.asarray(x), dtype=dt, device="cuda")
+
+
+def _rel(a, b):
+    return np.linalg.norm(a - b) / np.linalg.norm(b)
+
+
+@pytest.mark.parametrize("sample_major", [False, True])
+def test_features_match_oracle(sample_major):
+    ang = philox.sample_angles(5, 0, 37, 6)
+    B = [0.0, 1.5, 4.0]
+    x = rp.mlp_features(_t(ang, torch.float64), B, 19, sample_major=sample_major).cpu().numpy()
+    want = mlp.features(ang, B)
+    if sample_major:
+        want = want.reshape(3, 37, -1).transpose(1, 0, 2).reshape(111, -1)
+    assert np.max(np.abs(x - want)) < 1e-6
+
+
+def _net(n_in=19, width=64, depth=3, seed=1):
+    rng = np.random.default_rng(seed)
+    p = mlp.init_params(n_in, width, depth, rng)
+    p += rng.normal(0, 0.02, len(p))
+    return p
+
+
+def test_forward_matches_fp64_oracle():
+    n_in, width, depth = 19, 64, 3
+    p = _net(n_in, width, depth)
+    rng = np.random.default_rng(2)
+    x = rng.normal(0, 1, (100, mlp.in_pad(n_in)))
+    _say("mlp forward")
+    y = rp.mlp_forward(_t(p), _t(x), n_in, width, depth).cpu().numpy()
+    want, _ = mlp.forward(p.astype(np.float32).astype(float), x.astype(np.float32).astype(float), n_in, width, depth)
+    assert _rel(y, want) < 3e-2
+
+
+def test_gradient_and_adam_match_oracle():
+    n_in, width, depth = 19, 64, 3
+    p = _net(n_in, width, depth, seed=4)
+    rng = np.random.default_rng(3)
+    x = rng.normal(0, 1, (96, mlp.in_pad(n_in)))
+    t = rng.normal(0, 1, 96)
+    P, Mo, V = _t(p), torch.zeros(len(p), device="cuda"), torch.zeros(len(p), device="cuda")
+    G = torch.empty(len(p), device="cuda")
+    err = torch.empty(96, device="cuda")
+    _say("mlp gradient")
+    rp.mlp_train_step(P, Mo, V, 1, _t(x), _t(t), n_in, width, depth, lr=0.0, grad_out=G, sq_err=err)
+    p32 = p.astype(np.float32).astype(float)
+    loss, g = mlp.loss_and_grad(p32, x.astype(np.float32).astype(float), t, n_in, width, depth)
+    assert _rel(G.cpu().numpy(), g) < 5e-2
+    assert abs(err.cpu().numpy().mean() - loss) < 5e-2 * loss
+    assert np.array_equal(P.cpu().numpy(), p.astype(np.float32))         # lr = 0 leaves parameters alone
+    # one real Adam step: parameters follow the oracle's Adam applied to the GPU gradient
+    rp.mlp_train_step(P, Mo, V, 1, _t(x), _t(t), n_in, width, depth, lr=1e-3, grad_out=G)
+    gg = G.cpu().numpy().astype(float)
+    want, _, _ = mlp.adam(p.astype(np.float32).astype(float), np.zeros(len(p)), np.zeros(len(p)), gg, 1, 1e-3)
+    assert np.max(np.abs(P.cpu().numpy() - want)) < 1e-6
+
+
+def test_training_reduces_loss():
+    n_in, width, depth = 7, 64, 2
+    rng = np.random.default_rng(8)
+    x = rng.normal(0, 1, (1024, 16))
+    x[:, n_in:] = 0.0
+    t = np.sin(x[:, 0]) * x[:, 1] + 0.3 * x[:, 2] ** 2
+    p = mlp.init_params(n_in, width, depth, rng)
+    P, Mo, V = _t(p), torch.zeros(len(p), device="cuda"), torch.zeros(len(p), device="cuda")
+    X, T = _t(x), _t(t)
+    err = torch.empty(256, device="cuda")
+    _say("mlp training")
+    first = None
+    for step in range(1, 401):
+        i = (step * 256) % 1024
+        rp.mlp_train_step(P, Mo, V, step, X[i:i + 256], T[i:i + 256], n_in, width, depth, lr=3e-3, sq_err=err)
+        if step == 1:
+            first = float(err.mean())
+    y = rp.mlp_forward(P, X, n_in, width, depth).cpu().numpy()
+    assert np.mean((y - t) ** 2) < first / 10
+
+
+def test_control_variate_is_unbiased_and_reduces_variance():
+    """Trained on yields of stream 1, beta from held-out samples, mu from stream 2: the
+    estimate on stream 0 agrees with the Eq. 14 trace within 4 standard errors and its
+    standard error is well below the plain Monte Carlo error of the same samples."""
+    s = SpinSystem(3, 3, [1] * 6, [0.9, -0.6, 0.35, 0.7, -0.45, 0.2], kS=2.0, kT=0.5, T_us=5.0)
+    B = np.array([0.0, 1.0, 2.5, 5.0])
+    c = cv.ControlVariate(s, B, seed=77, width=64, depth=3)
+    _say("cv: generate")
+    a_tr, phi_tr = c.generate(2048)
+    _say("cv: train")
+    c.train(a_tr, phi_tr, epochs=80, batch=256, lr=2e-3)
+    c.fit_mu(32768)
+    a_ev, phi_ev = c.generate(256, stream=cv.STREAM_EVAL)
+    m_cv, e_cv = (t.cpu().numpy() for t in c.estimate(a_ev, phi_ev))
+    m_pl, e_pl = (t.cpu().numpy() for t in rp.yield_stats(phi_ev))
+    d = spin.DenseSystem((3, 3), s.two_I, s.a_mT, kS=s.kS, kT=s.kT)
+    exact = np.array([yields.FieldOracle(d, b, s.T_us).trace_yield() for b in B])
+    _say("cv", m_cv, e_cv, "plain", m_pl, e_pl, "exact", exact, "val mse", c.val_mse)
+    assert np.all(np.abs(m_cv - exact) < 4 * e_cv + 1e-5)
+    assert np.all(np.abs(m_pl - exact) < 4 * e_pl + 1e-5)
+    # gain: every field improves, and on average the samples needed for a given error fall >= 4x
+    assert np.all(e_cv < 0.75 * e_pl)
+    assert np.mean((e_cv / e_pl) ** 2) < 0.25
+    # the estimator is the oracle's formula applied to the same numbers
+    g = c.g(a_ev).cpu().numpy()
+    wm, we = stats.cv_mean_error(phi_ev.cpu().numpy(), g, c.mu.cpu().numpy(), c.beta.cpu().numpy(),
+                                 c.mu_err.cpu().numpy())
+    assert np.max(np.abs(wm - m_cv)) < 1e-12 and np.max(np.abs(we - e_cv)) < 1e-12

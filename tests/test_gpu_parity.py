@@ -142,6 +142,10 @@ def test_yield_statistics():
     m, e = rp.yield_stats(T(phi), T(g), T(mu), T(be))
     wm, we = stats.cv_mean_error(phi, g, mu, be)
     assert np.max(np.abs(m.cpu().numpy() - wm)) < 1e-14 and np.max(np.abs(e.cpu().numpy() - we)) < 1e-14
+    me = rng.uniform(0, 0.01, 5)
+    m, e = rp.yield_stats(T(phi), T(g), T(mu), T(be), T(me))
+    wm, we = stats.cv_mean_error(phi, g, mu, be, me)
+    assert np.max(np.abs(m.cpu().numpy() - wm)) < 1e-14 and np.max(np.abs(e.cpu().numpy() - we)) < 1e-14
 
 
 def test_underestimated_spectrum_is_reported():

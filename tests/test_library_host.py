@@ -134,7 +134,7 @@ def test_argument_validation_without_device():
     assert L.rp_sample(ctypes.byref(cs.c), 1, 0, 0, 4, 7, fake, None) == rp.RP_EINVAL
     big = rp._CSystem(SpinSystem(1, 0, [5], [0.1]))
     assert L.rp_sample(ctypes.byref(big.c), 1, 0, 0, 4, 0, fake, None) == rp.RP_EINVAL
-    assert L.rp_yield(None, 3, 4, None, None, None, fake, fake, None) == rp.RP_EINVAL
-    assert L.rp_yield(fake, 3, 4, fake, None, None, fake, fake, None) == rp.RP_EINVAL
+    assert L.rp_yield(None, 3, 4, None, None, None, None, fake, fake, None) == rp.RP_EINVAL
+    assert L.rp_yield(fake, 3, 4, fake, None, None, None, fake, fake, None) == rp.RP_EINVAL
     assert b"two_I" in L.rp_last_error() or len(L.rp_last_error()) > 0
     assert L.rp_strerror(rp.RP_ENOTCONV).startswith(b"propagation")
