@@ -85,6 +85,78 @@ def summarize(path):
     return out
 
 
+def cv_headline(args):
+    """Sweep wall time to eps <= 1e-3 at every field: FP32 + learned control variate (training
+    included) against plain FP64 and plain FP32 Monte Carlo, on the control-variate workload
+    (the first N=14 system of the batched set, 32 fields).  Rates and standard deviations are
+    measured here; the wall times follow from them as M_needed * fields / rate."""
+    import torch
+    from paper_1612_09517_amd import cv, rp, workloads
+    w = workloads.cv_c5()
+    s = w.systems[0]
+    B = w.fields_mT[0]
+    nB = len(B)
+    torch.cuda.set_device(0)
+    c = cv.ControlVariate(s, B, seed=w.seed, width=256, depth=3, precision=32)
+    n_train = args.cv_train // nB
+    sync = torch.cuda.synchronize
+    sync()
+    t0 = time.perf_counter()
+
+    def say(msg):
+        print(json.dumps({"progress": msg, "t_s": round(time.perf_counter() - t0, 1)}), flush=True)
+
+    a_tr, phi_tr = c.generate_training(n_train, progress=lambda d, n: say(f"training yields: field {d}/{n}"))
+    sync()
+    t_gen = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    val = c.train(a_tr, phi_tr, epochs=args.cv_epochs, batch=512, lr=1e-3)
+    sync()
+    t_train = time.perf_counter() - t0
+    say(f"trained: validation mse {val:.4f} (standardised), {len(c.history)} epochs")
+    t0 = time.perf_counter()
+    c.fit_mu(args.cv_quad)
+    sync()
+    t_mu = time.perf_counter() - t0
+    say("mu fitted")
+    Me = args.cv_eval
+    t0 = time.perf_counter()
+    a_ev = rp.sample(s, w.seed, Me, stream_id=cv.STREAM_EVAL)
+    phi_ev = rp.propagate(s, B[None, :], a_ev, Me, precision=32)[0]
+    sync()
+    rate32 = Me * nB / (time.perf_counter() - t0)
+    say(f"evaluation samples done, {rate32:.1f} propagations/s")
+    m_cv, e_cv = (x.cpu().numpy() for x in c.estimate(a_ev, phi_ev))
+    m_pl, e_pl = (x.cpu().numpy() for x in rp.yield_stats(phi_ev))
+    M64 = max(4, Me // 8)
+    t0 = time.perf_counter()
+    a64 = rp.sample(s, w.seed, M64, first=10 ** 6, stream_id=cv.STREAM_EVAL)
+    rp.propagate(s, B[None, :], a64, M64, precision=64)
+    sync()
+    rate64 = M64 * nB / (time.perf_counter() - t0)
+    sig_pl = e_pl * np.sqrt(Me)
+    sig_cv = e_cv * np.sqrt(Me)        # includes the (small) contribution of mu's error
+    eps = 1e-3
+    M_pl = float(np.ceil(np.max((sig_pl / eps) ** 2)))
+    M_cv = float(np.ceil(np.max((sig_cv / eps) ** 2)))
+    wall64 = M_pl * nB / rate64
+    wall32 = M_pl * nB / rate32
+    wall_cv = t_gen + t_train + t_mu + M_cv * nB / rate32
+    rec = {"metric": "sweep wall time at sigma(Phi_S)<=1e-3: FP32 + learned control variate vs plain FP64 MC",
+           "value": wall_cv, "unit": "s", "higher_is_better": False, "n_gpus": 1, "data": "synthetic",
+           "dtype": "f32", "config": {"workload": w.name + ": N=14 spin-1/2, Z=16384, 32 fields 0..5 mT",
+                                      "kS": s.kS, "kT": s.kT, "T_us": s.T_us, "train_yields": n_train * nB,
+                                      "eval_samples": Me, "mu_samples": args.cv_quad, "net": "3x256 GELU, BF16 MFMA"},
+           "plain_fp64_wall_s": wall64, "plain_fp32_wall_s": wall32, "speedup_vs_fp64": wall64 / wall_cv,
+           "rate_fp32_props_s": rate32, "rate_fp64_props_s": rate64,
+           "train_s": {"generate": t_gen, "fit": t_train, "mu": t_mu}, "val_mse_standardised": val,
+           "samples_needed": {"plain": M_pl, "cv": M_cv},
+           "sigma_plain_max": float(sig_pl.max()), "sigma_cv_max": float(sig_cv.max()),
+           "variance_ratio_mean": float(np.mean((e_cv / e_pl) ** 2)),
+           "cv_minus_plain_over_err": float(np.max(np.abs(m_cv - m_pl) / np.sqrt(e_cv ** 2 + e_pl ** 2)))}
+    print(json.dumps(rec), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -99,12 +171,21 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe", type=float, default=0.0,
                     help="only copy a buffer of this many GiB three times (calibrates HBM counters)")
+    ap.add_argument("--cv", action="store_true",
+                    help="headline comparison: FP32 + learned control variate vs plain FP64 sweep wall time")
+    ap.add_argument("--cv-train", type=int, default=4096, help="training yields (one direction each)")
+    ap.add_argument("--cv-epochs", type=int, default=60)
+    ap.add_argument("--cv-quad", type=int, default=65536, help="samples for the mean of the network")
+    ap.add_argument("--cv-eval", type=int, default=128, help="evaluation samples (pilot)")
     ap.add_argument("--summarize", default="",
                     help="print a per-kernel summary of a rocprofv3 CSV directory and exit")
     args = ap.parse_args()
     if args.summarize:
         for k, v in sorted(summarize(args.summarize).items(), key=lambda kv: -kv[1].get("pct", 0)):
             print(json.dumps({"kernel": k, **v}))
+        return
+    if args.cv:
+        cv_headline(args)
         return
     if args.copy_probe > 0:
         import torch

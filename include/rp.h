@@ -157,9 +157,10 @@ int rp_yield(const double *phi, int32_t nB, int64_t M, const double *cv_g, const
  * rp_mlp_param_count     number of packed parameters (-1 for a bad shape: width must be a
  *                        positive multiple of 16, 1 <= depth <= 8).
  * rp_mlp_workspace_floats  FP32 workspace needed by forward/train calls on `rows` rows.
- * rp_mlp_features        x[row][0 .. n_in_pad) (device) for every field b and sample s, from a
- *                        device [M][N][2] angle array and device fields B_mT [nB]; row = b*M + s,
- *                        or s*nB + b when sample_major != 0 (training batches then mix fields).
+ * rp_mlp_features        x[row][0 .. n_in_pad) (device), nB*M rows, device fields B_mT [nB]:
+ *                        layout 0: [M][N][2] angles shared by all fields, row = b*M + s;
+ *                        layout 1: the same angles, row = s*nB + b (batches mix fields);
+ *                        layout 2: [nB*M][N][2] angles, one per row, row r has field r % nB.
  * rp_mlp_forward         y[rows] = g(x) (device).
  * rp_mlp_train_step      one Adam step (beta1 0.9, beta2 0.999, eps 1e-8; step >= 1 is the
  *                        Adam time step) on the batch (x, target); optional device outputs:
@@ -170,7 +171,7 @@ int rp_yield(const double *phi, int32_t nB, int64_t M, const double *cv_g, const
 int64_t rp_mlp_param_count(int32_t n_in, int32_t width, int32_t depth);
 int64_t rp_mlp_workspace_floats(int32_t n_in, int32_t width, int32_t depth, int64_t rows);
 int rp_mlp_features(const double *angles, int64_t M, int32_t N, const double *B_mT, int32_t nB,
-                    int32_t n_in_pad, int32_t sample_major, float *x, void *hip_stream);
+                    int32_t n_in_pad, int32_t layout, float *x, void *hip_stream);
 int rp_mlp_forward(int32_t n_in, int32_t width, int32_t depth, const float *params, const float *x,
                    int64_t rows, float *y, float *workspace, void *hip_stream);
 int rp_mlp_train_step(int32_t n_in, int32_t width, int32_t depth, float *params, float *adam_m,

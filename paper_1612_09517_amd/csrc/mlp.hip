@@ -165,7 +165,7 @@ struct FeatArgs {
   const double *angles, *B;
   float *x;
   int64_t M;
-  int32_t N, nB, n_in_pad, sample_major;
+  int32_t N, nB, n_in_pad, layout;
 };
 
 __global__ __launch_bounds__(256) void k_features(FeatArgs f) {
@@ -174,8 +174,8 @@ __global__ __launch_bounds__(256) void k_features(FeatArgs f) {
   if (i >= rows * f.n_in_pad) return;
   const int64_t r = i / f.n_in_pad;
   const int c = (int)(i - r * f.n_in_pad);
-  const int64_t b = f.sample_major ? r % f.nB : r / f.M;
-  const int64_t s = f.sample_major ? r / f.nB : r - b * f.M;
+  const int64_t b = f.layout == 0 ? r / f.M : r % f.nB;
+  const int64_t s = f.layout == 0 ? r - b * f.M : f.layout == 1 ? r / f.nB : r;
   float v = 0.f;
   if (c < 3 * f.N) {
     const int k = c / 3, q = c - 3 * k;
@@ -265,11 +265,12 @@ extern "C" int64_t rp_mlp_workspace_floats(int32_t n_in, int32_t width, int32_t 
 }
 
 extern "C" int rp_mlp_features(const double *angles, int64_t M, int32_t N, const double *B_mT, int32_t nB,
-                               int32_t n_in_pad, int32_t sample_major, float *x, void *hip_stream) {
+                               int32_t n_in_pad, int32_t layout, float *x, void *hip_stream) {
   if (M < 0 || N < 0 || nB < 0 || n_in_pad < 3 * N + 1) return mlp_fail(RP_EINVAL, "bad feature sizes");
+  if (layout < 0 || layout > 2) return mlp_fail(RP_EINVAL, "layout must be 0, 1 or 2");
   if (M == 0 || nB == 0) return RP_OK;
   if (!angles || !B_mT || !x) return mlp_fail(RP_EINVAL, "null pointer");
-  FeatArgs f{angles, B_mT, x, M, N, nB, n_in_pad, sample_major ? 1 : 0};
+  FeatArgs f{angles, B_mT, x, M, N, nB, n_in_pad, layout};
   hipLaunchKernelGGL(k_features, dim3(blocks((int64_t)nB * M * n_in_pad)), dim3(256), 0,
                      (hipStream_t)hip_stream, f);
   return hipGetLastError() == hipSuccess ? RP_OK : mlp_fail(RP_EDEVICE, "feature kernel launch failed");

@@ -2,18 +2,22 @@
 
 For one system and its field sweep:
 
-1. training data: single-wavepacket yields phi_S(Omega, B) from rp_propagate on samples of
-   Philox stream 1 (disjoint from the evaluation stream 0);
+1. training data: single-wavepacket yields phi_S(Omega_r, B_{r mod nB}) from rp_propagate,
+   one direction per yield (sample r of Philox stream 1, disjoint from the evaluation
+   stream 0), so that n training yields see n distinct directions;
 2. training: the network g(Omega, B) of rp_mlp_* fitted by Adam on mean squared error of
-   standardised targets, with the last 10 % of samples held out for early stopping;
-3. beta_B = Cov(phi, g)/Var(g) per field on the held-out samples (rp_cv_beta);
+   targets standardised per field (the fit then measures within-field fluctuations, the
+   part a control variate can remove), the last 10 % of yields held out for early stopping;
+3. beta_B = Cov(phi, g)/Var(g) per field on the held-out yields (rp_cv_beta); beta absorbs the
+   per-field scale of g;
 4. mu_B = mean of g over K fresh directions of stream 2 (rp_mlp_forward, rp_yield), with its
    standard error;
 5. estimate: rp_yield(phi, g, mu, beta, err mu) on the evaluation samples, i.e.
    mean(phi - beta (g - mu)), unbiased because g, beta and mu do not depend on them.
 
-Every numerical step runs in librp kernels; this module only moves device buffers between
-calls, picks batches and keeps the best parameters (early stopping on a host-side scalar).
+Every numerical step of the method runs in librp kernels; this module moves device buffers
+between calls, standardises the training targets on the host, picks batches and keeps the
+best parameters (early stopping on a host-side scalar).
 """
 import numpy as np
 
@@ -48,19 +52,33 @@ class ControlVariate:
         self.m = torch.zeros_like(self.params)
         self.v = torch.zeros_like(self.params)
         self.step = 0
-        self.t_mean, self.t_std = 0.0, 1.0
         self.beta = self.mu = self.mu_err = None
         self.history = []
 
     # ------------------------------------------------------------------ data
-    def generate(self, n, stream=STREAM_TRAIN, first=0):
-        """(angles [n][N][2], phi [nB][n]) from the method itself."""
+    def generate(self, n, stream=STREAM_EVAL, first=0):
+        """Evaluation data: (angles [n][N][2], phi [nB][n]), every direction at every field."""
         ang = rp.sample(self.s, self.seed, n, first=first, stream_id=stream)
         phi = rp.propagate(self.s, self.B[None, :], ang, n, precision=self.precision)[0]
         return ang, phi
 
+    def generate_training(self, n_per_field, progress=None):
+        """Training data with one direction per yield: direction r (stream 1) at field r % nB.
+        Returns (angles [nB*n][N][2], phi [nB*n])."""
+        import torch
+        nB = self.nB
+        ang = rp.sample(self.s, self.seed, n_per_field * nB, stream_id=STREAM_TRAIN)
+        phi = torch.empty(n_per_field * nB, dtype=torch.float64, device="cuda")
+        for b in range(nB):
+            a_b = ang[b::nB].contiguous()
+            phi[b::nB] = rp.propagate(self.s, self.B[None, b:b + 1], a_b, n_per_field,
+                                      precision=self.precision)[0, 0]
+            if progress:
+                progress(b + 1, nB)
+        return ang, phi
+
     def g(self, angles):
-        """Network output for every (field, sample): float64 [nB][M]."""
+        """Network output for every (field, sample) of shared directions: float64 [nB][M]."""
         M = angles.shape[0]
         x = rp.mlp_features(angles, self.B, self.n_in)
         y = rp.mlp_forward(self.params, x, self.n_in, self.width, self.depth)
@@ -68,22 +86,26 @@ class ControlVariate:
 
     # ------------------------------------------------------------------ training
     def train(self, angles, phi, epochs=60, batch=512, lr=1e-3, val_frac=0.1, patience=10):
+        """Fits g on training data from generate_training; returns the best validation MSE in
+        units of the per-field variance (1 - R^2 within fields)."""
         import torch
-        n = angles.shape[0]
-        n_val = max(1, int(round(n * val_frac)))
-        n_tr = n - n_val
-        # Targets: the yields, standardised on the host (input preparation), row s*nB + b.
-        ph_h = phi.detach().cpu().numpy()
-        self.t_mean = float(ph_h[:, :n_tr].mean())
-        self.t_std = float(ph_h[:, :n_tr].std()) or 1.0
-        t = torch.tensor(((ph_h.T.reshape(-1) - self.t_mean) / self.t_std).astype(np.float32), device="cuda")
-        x = rp.mlp_features(angles, self.B, self.n_in, sample_major=True)
-        rows_tr = n_tr * self.nB
+        nB = self.nB
+        n_pf = phi.shape[0] // nB
+        n_val = max(2, int(round(n_pf * val_frac)))
+        n_tr = n_pf - n_val
+        rows_tr = n_tr * nB
+        # Targets standardised per field on the host (input preparation); row r has field r % nB.
+        ph = phi.detach().cpu().numpy().reshape(n_pf, nB)
+        mean = ph[:n_tr].mean(axis=0)
+        std = ph[:n_tr].std(axis=0)
+        std[std == 0] = 1.0
+        t = torch.tensor(((ph - mean) / std).reshape(-1).astype(np.float32), device="cuda")
+        x = rp.mlp_features(angles, self.B, self.n_in, layout=2)
         x_tr, t_tr = x[:rows_tr], t[:rows_tr]
-        x_va, t_va = x[rows_tr:], t[rows_tr:]
+        x_va = x[rows_tr:]
+        t_va_h = t[rows_tr:].cpu().numpy()
         ws = rp.mlp_workspace(self.n_in, self.width, self.depth, max(batch, x_va.shape[0]))
         best, best_p, bad = np.inf, self.params.clone(), 0
-        t_va_h = t_va.cpu().numpy()
         for ep in range(epochs):
             for i in range(0, rows_tr - batch + 1, batch):
                 self.step += 1
@@ -98,23 +120,19 @@ class ControlVariate:
                 bad += 1
                 if bad >= patience:
                     break
-        # Keep the best parameters and fold the target scaling into the output layer, so that
-        # g is on the scale of phi_S.
-        p = best_p.cpu().numpy().astype(np.float64)
-        p[-self.width - 1:-1] *= self.t_std
-        p[-1] = p[-1] * self.t_std + self.t_mean
-        self.params.copy_(torch.tensor(p.astype(np.float32), device="cuda"))
-        self.val_mse = best            # in units of the target variance: 1 - R^2 over all fields
-        # beta from the held-out samples (independent of any later evaluation set)
-        g_va = self.g(angles[n_tr:])
-        self.beta = rp.cv_beta(phi[:, n_tr:].contiguous(), g_va)
+        self.params.copy_(best_p)
+        self.val_mse = best
+        # beta per field from the held-out yields (independent of any later evaluation set)
+        y = rp.mlp_forward(self.params, x_va, self.n_in, self.width, self.depth, workspace=ws)
+        g_va = y.double().reshape(n_val, nB).t().contiguous()
+        phi_va = phi[rows_tr:].reshape(n_val, nB).t().contiguous()
+        self.beta = rp.cv_beta(phi_va, g_va)
         return best
 
     def fit_mu(self, K, first=0):
-        """mu_B = E[g(., B)] from K directions of the quadrature stream, and var(mu_B)."""
+        """mu_B = E[g(., B)] from K directions of the quadrature stream, and its standard error."""
         ang = rp.sample(self.s, self.seed, K, first=first, stream_id=STREAM_QUAD)
-        gq = self.g(ang)
-        self.mu, self.mu_err = rp.yield_stats(gq)
+        self.mu, self.mu_err = rp.yield_stats(self.g(ang))
         return self.mu, self.mu_err
 
     # ------------------------------------------------------------------ estimate

@@ -190,15 +190,16 @@ def mlp_workspace(n_in, width, depth, rows):
     return torch.empty(max(n, 1), dtype=torch.float32, device="cuda")
 
 
-def mlp_features(angles, B_mT, n_in, sample_major=False):
-    """rp_mlp_features: [nB*M][n_in_pad] float32 features (field-major rows unless sample_major)."""
+def mlp_features(angles, B_mT, n_in, layout=0):
+    """rp_mlp_features: [nB*M][n_in_pad] float32 features (row layouts 0, 1, 2 of rp.h)."""
     import torch
-    M, N = angles.shape[0], angles.shape[1]
     B = torch.as_tensor(np.asarray(B_mT, np.float64).reshape(-1), device="cuda")
     nB = B.numel()
+    N = angles.shape[1]
+    M = angles.shape[0] // nB if layout == 2 else angles.shape[0]
     x = torch.empty((nB * M, mlp_in_pad(n_in)), dtype=torch.float32, device="cuda")
     _check(lib().rp_mlp_features(_dev_ptr(angles.contiguous(), torch.float64), M, N, _dev_ptr(B, torch.float64),
-                                 nB, x.shape[1], 1 if sample_major else 0, _dev_ptr(x, torch.float32),
+                                 nB, x.shape[1], int(layout), _dev_ptr(x, torch.float32),
                                  _stream(torch)))
     return x
 

@@ -38,14 +38,17 @@ def _rel(a, b):
     return np.linalg.norm(a - b) / np.linalg.norm(b)
 
 
-@pytest.mark.parametrize("sample_major", [False, True])
-def test_features_match_oracle(sample_major):
-    ang = philox.sample_angles(5, 0, 37, 6)
+@pytest.mark.parametrize("layout", [0, 1, 2])
+def test_features_match_oracle(layout):
     B = [0.0, 1.5, 4.0]
-    x = rp.mlp_features(_t(ang, torch.float64), B, 19, sample_major=sample_major).cpu().numpy()
-    want = mlp.features(ang, B)
-    if sample_major:
-        want = want.reshape(3, 37, -1).transpose(1, 0, 2).reshape(111, -1)
+    ang = philox.sample_angles(5, 0, 37 * (3 if layout == 2 else 1), 6)
+    x = rp.mlp_features(_t(ang, torch.float64), B, 19, layout=layout).cpu().numpy()
+    if layout == 2:      # row r: direction r, field r % 3
+        want = np.concatenate([mlp.features(ang[r:r + 1], [B[r % 3]]) for r in range(111)])
+    else:
+        want = mlp.features(ang, B)
+        if layout == 1:
+            want = want.reshape(3, 37, -1).transpose(1, 0, 2).reshape(111, -1)
     assert np.max(np.abs(x - want)) < 1e-6
 
 
@@ -119,7 +122,7 @@ def test_control_variate_is_unbiased_and_reduces_variance():
     B = np.array([0.0, 1.0, 2.5, 5.0])
     c = cv.ControlVariate(s, B, seed=77, width=64, depth=3)
     _say("cv: generate")
-    a_tr, phi_tr = c.generate(2048)
+    a_tr, phi_tr = c.generate_training(512)
     _say("cv: train")
     c.train(a_tr, phi_tr, epochs=80, batch=256, lr=2e-3)
     c.fit_mu(32768)
