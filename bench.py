@@ -157,6 +157,52 @@ def cv_headline(args):
     print(json.dumps(rec), flush=True)
 
 
+def other_workload(args):
+    """Throughput of the other workloads (one JSON line each): the tiny Z=8 system, a strided
+    subset of the 256 uneven systems (one call: small systems in the LDS-resident launches,
+    larger ones tiled), a subset of the large spin-1 system, and the paper's Table I model."""
+    import torch
+    from paper_1612_09517_amd import rp, workloads
+    torch.cuda.set_device(0)
+    name = args.workload
+    if name == "tiny":
+        w = workloads.tiny_c1()
+        systems, B, M = w.systems, w.fields_mT, w.M
+    elif name == "batched":
+        w = workloads.batched_c3()
+        sel = [i for i in range(0, len(w.systems), args.stride) if w.systems[i].N <= args.max_n]
+        systems = [w.systems[i] for i in sel]
+        B, M = w.fields_mT[sel], args.samples_per_step
+    elif name == "large":
+        w = workloads.large_c4(n_fields=args.fields)
+        systems, B, M = w.systems, w.fields_mT, args.samples_per_step
+    elif name == "paper":
+        w = workloads.paper_model(n_fields=args.fields)
+        systems, B, M = w.systems, w.fields_mT, args.samples_per_step
+    else:
+        raise SystemExit("unknown workload " + name)
+    angs = [rp.sample(s, w.seed + i, M) for i, s in enumerate(systems)]
+    cat = torch.cat([a.reshape(-1) for a in angs])
+    for _ in range(args.warmup):
+        rp.propagate(systems, B, cat, M, precision=args.precision)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        phi = rp.propagate(systems, B, cat, M, precision=args.precision)
+        mean, err = rp.yield_stats(phi.reshape(-1, M))
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / args.steps
+    props = len(systems) * B.shape[1] * M
+    Zs = [s.Z for s in systems]
+    rec = {"metric": "propagations per second", "value": props / dt, "unit": "propagations/s",
+           "higher_is_better": True, "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": dt * 1e3, "dtype": "f32" if args.precision == 32 else "f64", "data": "synthetic",
+           "config": {"workload": w.name, "systems": len(systems), "fields": int(B.shape[1]), "samples": M,
+                      "Z_min": min(Zs), "Z_max": max(Zs)},
+           "phi_mean_first_system": [round(float(x), 6) for x in mean[:B.shape[1]].cpu().numpy()][:8]}
+    print(json.dumps(rec), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -171,6 +217,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe", type=float, default=0.0,
                     help="only copy a buffer of this many GiB three times (calibrates HBM counters)")
+    ap.add_argument("--workload", default="sweep", choices=["sweep", "tiny", "batched", "large", "paper"])
+    ap.add_argument("--stride", type=int, default=8, help="batched workload: take every stride-th system")
+    ap.add_argument("--max-n", type=int, default=12, help="batched workload: only systems with at most this many nuclei")
     ap.add_argument("--cv", action="store_true",
                     help="headline comparison: FP32 + learned control variate vs plain FP64 sweep wall time")
     ap.add_argument("--cv-train", type=int, default=4096, help="training yields (one direction each)")
@@ -186,6 +235,9 @@ def main():
         return
     if args.cv:
         cv_headline(args)
+        return
+    if args.workload != "sweep":
+        other_workload(args)
         return
     if args.copy_probe > 0:
         import torch

@@ -80,6 +80,11 @@ typedef struct rp_opts {
 /* opts->flags: record HIP events around the Chebyshev-term launches of every step
    and keep the totals for rp_profile_last (adds a few event records per step). */
 #define RP_FLAG_PROFILE 1
+/* opts->flags: use the tiled kernels for every system.  Without it, systems with at most
+   1024 (complex FP32) or 512 (FP64) nuclear states run in the LDS-resident kernel: one
+   workgroup per wavepacket for the whole propagation, every such job of the call in one
+   launch per workgroup size.  Profiled calls always use the tiled kernels. */
+#define RP_FLAG_TILED 2
 
 /*
  * rp_sample -- directions of the nuclear coherent states (Eq. 18: uniform on

@@ -94,4 +94,46 @@ struct FinArgs {
   double kS, kmin, rtol;
 };
 
+// ---------------------------------------------------------------- LDS-resident propagation
+// Small systems (Z <= kResMax32 for complex FP32, kResMax64 for FP64): one workgroup per job
+// runs the whole propagation with the wavepacket in LDS; jobs of several systems, fields and
+// samples share one launch.
+constexpr int kResMax32 = 1024;
+constexpr int kResMax64 = 512;
+constexpr int kResRank = 32;   // quadrature columns held in registers per thread
+
+template <typename R>
+struct ResSys {
+  SysArgs<R> sa;
+  int64_t tab_off;     // offset (in coherent-table rows of RP_MAX_TWO_I+1) of this system's samples
+  double kS, kmin, rtol;
+};
+
+template <typename R>
+struct ResField {
+  FieldDev<R> fd;
+  double dt;
+  int64_t coef_off;    // into the coefficient array (n_terms entries)
+  int64_t ell_off;     // into the quadrature factor array (n_terms x kResRank entries)
+  int32_t n_steps, n_terms;
+};
+
+struct ResJob {
+  int32_t sys, field, sample, pad;
+  int64_t out;         // index into phi
+};
+
+template <typename R>
+struct ResArgs {
+  const ResSys<R> *sys;
+  const ResField<R> *fields;
+  const ResJob *jobs;
+  const cx<R> *coef;
+  const R *ell;
+  const cx<double> *tab;
+  double *phi;
+  int *flag;
+  int64_t njobs;
+};
+
 }  // namespace rp

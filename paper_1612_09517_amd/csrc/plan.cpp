@@ -270,8 +270,8 @@ static std::vector<double> pivoted_cholesky(const std::vector<double> &A, int n,
   return L;
 }
 
-bool plan_field(const SystemSpec &s, double B_mT, double tol, double rdt, double r_scale,
-                double chol_tol, FieldPlan &out, std::string &msg) {
+static bool plan_field_once(const SystemSpec &s, double B_mT, double tol, double rdt, double r_scale,
+                            double chol_tol, FieldPlan &out, std::string &msg, double &log_growth) {
   out = FieldPlan();
   out.B_mT = B_mT;
   out.omega = s.gamma * std::fabs(B_mT);
@@ -308,6 +308,7 @@ bool plan_field(const SystemSpec &s, double B_mT, double tol, double rdt, double
   bessel_j(out.x, nmax, J.data());
   int N = 1;
   double lg = std::log(growth);
+  log_growth = lg;
   for (int n = nmax; n >= 1; --n) {
     double term = 2.0 * std::fabs(J[n]) * std::exp(n * lg);
     if (term > tol) {
@@ -320,6 +321,7 @@ bool plan_field(const SystemSpec &s, double B_mT, double tol, double rdt, double
     return false;
   }
   out.n_terms = N + 1;
+  log_growth = lg * N;   // worst-case growth of |T_n| over the step, on the spectral rectangle
   // a_n = (2 - delta_n0) (-i)^n J_n(x) exp(-i c dt)
   const std::complex<double> ph = std::exp(std::complex<double>(out.c_im * out.dt, -out.c_re * out.dt));
   const std::complex<double> mi(0.0, -1.0);
@@ -363,6 +365,20 @@ bool plan_field(const SystemSpec &s, double B_mT, double tol, double rdt, double
   for (int n = 0; n < nt; ++n) {
     const double f = (n == 0 ? 1.0 : 2.0) * M_SQRT1_2;
     for (int r = 0; r < rank; ++r) out.ell[(size_t)n * rank + r] = f * L[(size_t)n * rank + r];
+  }
+  return true;
+}
+
+bool plan_field(const SystemSpec &s, double B_mT, double tol, double rdt, double r_scale, double chol_tol,
+                double max_growth, FieldPlan &out, std::string &msg) {
+  // Strong dissipation (|kS - kT| comparable to the spectral width) makes T_n(Gh) grow on the
+  // imaginary extent of the spectrum; rounding errors grow with it.  Shorten the step until the
+  // worst-case growth over one step is at most max_growth.
+  double lg = 0.0;
+  for (int tries = 0; tries < 40; ++tries) {
+    if (!plan_field_once(s, B_mT, tol, rdt, r_scale, chol_tol, out, msg, lg)) return false;
+    if (lg <= std::log(max_growth) || rdt < 2.0) return true;
+    rdt *= 0.8;
   }
   return true;
 }

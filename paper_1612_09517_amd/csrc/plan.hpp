@@ -56,10 +56,11 @@ SystemSpec make_spec(int N1, int N2, const int32_t *two_I, const double *a_mT, d
 // J_0 + 2 sum_k J_2k = 1.
 void bessel_j(double x, int nmax, double *out);
 
-// Plans one field.  tol: truncation tolerance; rdt: target r dt; r_scale: multiplies rho.
+// Plans one field.  tol: truncation tolerance; rdt: target r dt (shortened while the worst-case
+// growth of the Chebyshev polynomials over one step exceeds max_growth); r_scale multiplies rho.
 // Returns false (with msg) on failure.
 bool plan_field(const SystemSpec &s, double B_mT, double tol, double rdt, double r_scale,
-                double chol_tol, FieldPlan &out, std::string &msg);
+                double chol_tol, double max_growth, FieldPlan &out, std::string &msg);
 
 // Upper bound on the spectral radius of H at field omega:
 // |omega| + sum_k |a_k| (I_k + 1)/2 + 3|J|/2 (triangle inequality over Eq. 1 terms,

@@ -533,6 +533,205 @@ static void launch_quad(int rcw, unsigned grid, hipStream_t st, const QuadArgs<R
   }
 }
 
+// ----------------------------------------------------------------------------- LDS-resident propagation
+// Sum over a workgroup of up to 1024 threads (every thread must call it).
+__device__ __forceinline__ double block_sum_any(double v, double *lds) {
+  v = warp_sum(v);
+  const int w = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
+  if ((threadIdx.x & 63) == 0) lds[w] = v;
+  __syncthreads();
+  double t = 0.0;
+  for (int i = 0; i < nw; ++i) t += lds[i];
+  __syncthreads();
+  return t;
+}
+
+// One workgroup propagates one wavepacket for all of its steps.  Thread M owns nuclear index M:
+// its four components of phi_n and phi_{n-1}, of the step accumulator and its kResRank
+// quadrature sums stay in registers; the components of phi_n are exchanged with the partners
+// through a ping-pong LDS buffer, one barrier per term.
+template <typename R, int MAXB, int RK>
+__global__ __launch_bounds__(MAXB) void k_resident(ResArgs<R> ra) {
+  extern __shared__ unsigned char smem_raw[];
+  cx<R> *buf = reinterpret_cast<cx<R> *>(smem_raw);   // [2][4][Zb]
+  __shared__ double lds[16];
+  const int Zb = blockDim.x;
+  const ResJob jb = ra.jobs[blockIdx.x];
+  const int si = __builtin_amdgcn_readfirstlane(jb.sys);
+  const int fi = __builtin_amdgcn_readfirstlane(jb.field);
+  const SysArgs<R> &sa = ra.sys[si].sa;
+  const ResField<R> F = ra.fields[fi];
+  const FieldDev<R> fp = F.fd;
+  const int64_t Z = sa.Z;
+  const int M = threadIdx.x;
+  const bool live = M < Z;
+  const cx<R> zero = {R(0), R(0)};
+  const_ptr<R> ell = (const_ptr<R>)(ra.ell + F.ell_off);
+  const cx<R> *cf = ra.coef + F.coef_off;
+  const int N = sa.N;
+
+  // initial wavepacket |S> (x) prod_k |Omega_k>
+  cx<R> x0 = zero, x1 = zero, x2 = zero, x3 = zero;
+  if (live) {
+    const cx<double> *t = ra.tab + ra.sys[si].tab_off + (int64_t)jb.sample * N * (RP_MAX_TWO_I + 1);
+    cx<double> p = {M_SQRT1_2, 0.0};
+    int rem = M;
+    for (int k = 0; k < N; ++k) {
+      const int n = rem % sa.d[k];
+      rem /= sa.d[k];
+      const cx<double> c = t[k * (RP_MAX_TWO_I + 1) + n];
+      p = {p.x * c.x - p.y * c.y, p.x * c.y + p.y * c.x};
+    }
+    x1 = {R(p.x), R(p.y)};
+    x2 = {R(-p.x), R(-p.y)};
+  }
+  const double kS = ra.sys[si].kS, kmin = ra.sys[si].kmin, rtol = ra.sys[si].rtol;
+  double phi = 0.0, prev = 1.0 + 1e-6;
+  bool bad = false;
+  for (int step = 0; step < F.n_steps; ++step) {
+    // norm at the step start, and the wavepacket into buffer 0
+    double nrm = 0.0;
+    if (live) {
+      buf[M] = x0;
+      buf[Zb + M] = x1;
+      buf[2 * Zb + M] = x2;
+      buf[3 * Zb + M] = x3;
+      nrm = (double)x0.x * x0.x + (double)x0.y * x0.y + (double)x1.x * x1.x + (double)x1.y * x1.y +
+            (double)x2.x * x2.x + (double)x2.y * x2.y + (double)x3.x * x3.x + (double)x3.y * x3.y;
+    }
+    nrm = block_sum_any(nrm, lds);   // also orders the buffer writes before the first term
+    const double decay = exp(-kmin * step * F.dt);
+    if (!(decay * nrm <= prev * (1.0 + rtol) + 1e-300)) bad = true;
+    prev = decay * nrm;
+    cx<R> W[RK];
+#pragma unroll
+    for (int r = 0; r < RK; ++r) W[r] = zero;
+    cx<R> a0v = zero, a1v = zero, a2v = zero, a3v = zero;   // step accumulator
+    cx<R> o0 = zero, o1 = zero, o2 = zero, o3 = zero;       // phi_{n-1}
+    if (live) {   // term 0 contributes a_0 phi_0 and its singlet amplitude
+      const cx<R> c0 = cf[0];
+      a0v = cmul(c0, x0);
+      a1v = cmul(c0, x1);
+      a2v = cmul(c0, x2);
+      a3v = cmul(c0, x3);
+      const cx<R> d = csub(x1, x2);
+#pragma unroll
+      for (int r = 0; r < RK; ++r) {
+        const R l = ell[r];
+        W[r].x += l * d.x;
+        W[r].y += l * d.y;
+      }
+    }
+    for (int n = 0; n + 1 < F.n_terms; ++n) {
+      const cx<R> *cur = buf + (n & 1) * 4 * Zb;
+      cx<R> *nxt = buf + ((n + 1) & 1) * 4 * Zb;
+      if (live) {
+        cx<R> y0 = zero, y1 = zero, y2 = zero, y3 = zero;
+        R h1 = R(0), h2 = R(0);
+        int rem = M;
+        for (int k = 0; k < N; ++k) {
+          const int dk = sa.d[k], st = sa.stride[k];
+          const int nd = rem % dk;
+          rem /= dk;
+          const R mk = R(0.5) * R(dk - 1) - R(nd);
+          const bool r1 = k < sa.N1;
+          if (r1) h1 += sa.a[k] * mk; else h2 += sa.a[k] * mk;
+          if (nd > 0) {        // partner digit n-1: beta component -> alpha component
+            const R f = sa.f[k][nd - 1];
+            const int P = M - st;
+            if (r1) {
+              y0 = cadd(y0, cscale(f, cur[2 * Zb + P]));
+              y1 = cadd(y1, cscale(f, cur[3 * Zb + P]));
+            } else {
+              y0 = cadd(y0, cscale(f, cur[Zb + P]));
+              y2 = cadd(y2, cscale(f, cur[3 * Zb + P]));
+            }
+          }
+          if (nd < dk - 1) {   // partner digit n+1: alpha component -> beta component
+            const R f = sa.f[k][nd];
+            const int P = M + st;
+            if (r1) {
+              y2 = cadd(y2, cscale(f, cur[P]));
+              y3 = cadd(y3, cscale(f, cur[Zb + P]));
+            } else {
+              y1 = cadd(y1, cscale(f, cur[P]));
+              y3 = cadd(y3, cscale(f, cur[2 * Zb + P]));
+            }
+          }
+        }
+        const R hs = R(0.5) * (h1 + h2), hd = R(0.5) * (h1 - h2), hj = R(0.5) * sa.J;
+        y0 = cadd(y0, cscale(fp.omega + hs + hj, x0));
+        y1 = cadd(y1, cadd(cscale(hd - hj, x1), cscale(sa.J, x2)));
+        y2 = cadd(y2, cadd(cscale(-hd - hj, x2), cscale(sa.J, x1)));
+        y3 = cadd(y3, cscale(-fp.omega - hs + hj, x3));
+        const cx<R> tt = {R(0.5) * (x1.x - x2.x), R(0.5) * (x1.y - x2.y)};
+        const cx<R> ibt = {-sa.beta * tt.y, sa.beta * tt.x};
+        y1 = cadd(y1, ibt);
+        y2 = csub(y2, ibt);
+        const cx<R> c = {fp.c_re, fp.c_im};
+        const R s = n == 0 ? fp.s1 : fp.s2;
+        cx<R> z0 = cscale(s, csub(y0, cmul(c, x0)));
+        cx<R> z1 = cscale(s, csub(y1, cmul(c, x1)));
+        cx<R> z2 = cscale(s, csub(y2, cmul(c, x2)));
+        cx<R> z3 = cscale(s, csub(y3, cmul(c, x3)));
+        if (n > 0) {
+          z0 = csub(z0, o0);
+          z1 = csub(z1, o1);
+          z2 = csub(z2, o2);
+          z3 = csub(z3, o3);
+        }
+        nxt[M] = z0;
+        nxt[Zb + M] = z1;
+        nxt[2 * Zb + M] = z2;
+        nxt[3 * Zb + M] = z3;
+        const cx<R> an = cf[n + 1];
+        a0v = cadd(a0v, cmul(an, z0));
+        a1v = cadd(a1v, cmul(an, z1));
+        a2v = cadd(a2v, cmul(an, z2));
+        a3v = cadd(a3v, cmul(an, z3));
+        const cx<R> v = csub(z1, z2);
+        cx<R> u;
+        switch ((n + 1) & 3) {    // multiply by (-i)^(n+1)
+          case 0: u = v; break;
+          case 1: u = {v.y, -v.x}; break;
+          case 2: u = {-v.x, -v.y}; break;
+          default: u = {-v.y, v.x}; break;
+        }
+        const_ptr<R> e = ell + (int64_t)(n + 1) * kResRank;
+#pragma unroll
+        for (int r = 0; r < RK; ++r) {
+          const R l = e[r];
+          W[r].x += l * u.x;
+          W[r].y += l * u.y;
+        }
+        o0 = x0;
+        o1 = x1;
+        o2 = x2;
+        o3 = x3;
+        x0 = z0;
+        x1 = z1;
+        x2 = z2;
+        x3 = z3;
+      }
+      __syncthreads();
+    }
+    R part = R(0);
+#pragma unroll
+    for (int r = 0; r < RK; ++r) part += W[r].x * W[r].x + W[r].y * W[r].y;
+    const double y = block_sum_any(live ? (double)part : 0.0, lds);
+    phi += kS * decay * y;
+    if (!(y == y)) bad = true;
+    x0 = a0v;
+    x1 = a1v;
+    x2 = a2v;
+    x3 = a3v;
+  }
+  if (threadIdx.x == 0) {
+    ra.phi[jb.out] = phi;
+    if (bad) atomicOr(ra.flag, 1);
+  }
+}
+
 // ----------------------------------------------------------------------------- per-step finalisation
 __global__ __launch_bounds__(256) void k_finalize(FinArgs fa) {
   const int64_t job = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -697,7 +896,7 @@ static double gamma_of(const rp_system *s) { return s->gamma > 0.0 ? s->gamma : 
 
 struct Opts {
   int precision = 64, init_mode = 0, flags = 0;
-  double tol = 0, rdt = 80.0, r_scale = 1.0, chol_tol = 0;
+  double tol = 0, rdt = 80.0, r_scale = 1.0, chol_tol = 0, max_growth = 0;
   int64_t workspace = 0;
 };
 
@@ -711,7 +910,7 @@ static int read_opts(const rp_opts *o, Opts &out) {
     out.init_mode = o->init_mode;
     if (o->tol < 0 || o->rdt < 0 || o->r_scale < 0 || o->workspace_bytes < 0)
       return fail(RP_EINVAL, "negative option");
-    if ((o->flags & ~RP_FLAG_PROFILE) != 0 || o->reserved != 0)
+    if ((o->flags & ~(RP_FLAG_PROFILE | RP_FLAG_TILED)) != 0 || o->reserved != 0)
       return fail(RP_EINVAL, "unknown flags or nonzero reserved field");
     out.flags = o->flags;
     if (o->tol > 0) out.tol = o->tol;
@@ -721,6 +920,7 @@ static int read_opts(const rp_opts *o, Opts &out) {
   }
   if (out.tol == 0) out.tol = out.precision == 64 ? 1e-14 : 1e-9;
   out.chol_tol = out.precision == 64 ? 1e-17 : 1e-12;
+  out.max_growth = out.precision == 64 ? 1e4 : 1e2;
   if (out.rdt > 4000) return fail(RP_EINVAL, "rdt too large");
   return RP_OK;
 }
@@ -736,7 +936,7 @@ static int plan_all(const SystemSpec &spec, const double *B, int nB, const Opts 
   for (int t = 0; t < nth; ++t)
     th.emplace_back([&, t]() {
       for (int b = t; b < nB; b += nth)
-        ok[b] = plan_field(spec, B[b], op.tol, op.rdt, op.r_scale, op.chol_tol, plans[b], msgs[b]);
+        ok[b] = plan_field(spec, B[b], op.tol, op.rdt, op.r_scale, op.chol_tol, op.max_growth, plans[b], msgs[b]);
     });
   for (auto &x : th) x.join();
   for (int b = 0; b < nB; ++b)
@@ -1060,6 +1260,187 @@ static int propagate_system(const SystemSpec &spec, const double *B, int nB, con
   return RP_OK;
 }
 
+
+// Quadrature columns the resident kernel keeps per thread: 32 up to 512-thread workgroups, 24 for
+// 1024 threads (register budget 128 per lane).
+static int res_rank_limit(int64_t Z) { return Z > 512 ? 24 : kResRank; }
+
+// Propagates all jobs of the LDS-resident systems `idx` (one launch per block-size class).
+template <typename R>
+static int propagate_resident(const std::vector<int> &idx, const rp_system *sys, const double *B_mT, int nB,
+                              const double *angles, const std::vector<int64_t> &aoff, int64_t M, const Opts &op,
+                              double *phi, hipStream_t st) {
+  const int ns = (int)idx.size();
+  std::vector<SystemSpec> specs;
+  for (int i : idx)
+    specs.push_back(make_spec(sys[i].n_nuc[0], sys[i].n_nuc[1], sys[i].two_I, sys[i].a_mT, sys[i].J_mT, sys[i].kS,
+                              sys[i].kT, sys[i].T_us, gamma_of(&sys[i])));
+  // Plan every (system, field) with a step short enough that the quadrature rank fits kResRank.
+  std::vector<FieldPlan> plans((size_t)ns * nB);
+  std::vector<std::string> msgs((size_t)ns * nB);
+  std::vector<char> ok((size_t)ns * nB, 0);
+  {
+    const int tot = ns * nB;
+    const int nth = std::max(1, std::min<int>(tot, (int)std::thread::hardware_concurrency()));
+    std::vector<std::thread> th;
+    for (int t = 0; t < nth; ++t)
+      th.emplace_back([&, t]() {
+        for (int q = t; q < tot; q += nth) {
+          const int i = q / nB, b = q % nB;
+          const int rmax = res_rank_limit(specs[i].Z);
+          double rdt = std::min(op.rdt, 40.0);
+          for (int tries = 0; tries < 12; ++tries) {
+            ok[q] = plan_field(specs[i], B_mT[(int64_t)idx[i] * nB + b], op.tol, rdt, op.r_scale, op.chol_tol,
+                               op.max_growth, plans[q], msgs[q]);
+            if (!ok[q] || plans[q].rank <= rmax) break;
+            rdt *= 0.75;
+          }
+          if (ok[q] && plans[q].rank > rmax) {
+            ok[q] = 0;
+            msgs[q] = "quadrature rank does not fit the resident kernel";
+          }
+        }
+      });
+    for (auto &x : th) x.join();
+  }
+  for (size_t q = 0; q < plans.size(); ++q)
+    if (!ok[q]) return fail(RP_EINVAL, "field plan: " + msgs[q]);
+  // Descriptors.
+  std::vector<ResSys<R>> rsys(ns);
+  std::vector<ResField<R>> rf((size_t)ns * nB);
+  std::vector<cx<R>> coef;
+  std::vector<R> ell;
+  int64_t tab_elems = 0;
+  const double rtol = op.precision == 64 ? 1e-9 : 1e-4;
+  for (int i = 0; i < ns; ++i) {
+    std::memset(&rsys[i], 0, sizeof(ResSys<R>));
+    rsys[i].sa = make_sysargs<R>(specs[i]);
+    rsys[i].tab_off = tab_elems;
+    rsys[i].kS = specs[i].kS;
+    rsys[i].kmin = std::min(specs[i].kS, specs[i].kT);
+    rsys[i].rtol = rtol;
+    tab_elems += M * std::max(specs[i].N(), 1) * (RP_MAX_TWO_I + 1);
+    const double dk = std::fabs(specs[i].kS - specs[i].kT);
+    for (int b = 0; b < nB; ++b) {
+      const FieldPlan &p = plans[(size_t)i * nB + b];
+      ResField<R> &f = rf[(size_t)i * nB + b];
+      std::memset(&f, 0, sizeof(f));
+      f.fd.omega = (R)p.omega;
+      f.fd.c_re = (R)p.c_re;
+      f.fd.c_im = (R)(p.c_im + (specs[i].kS >= specs[i].kT ? 0.0 : 0.5 * dk));
+      f.fd.s1 = (R)(1.0 / p.r);
+      f.fd.s2 = (R)(2.0 / p.r);
+      f.dt = p.dt;
+      f.n_steps = (int32_t)p.n_steps;
+      f.n_terms = p.n_terms;
+      f.coef_off = (int64_t)coef.size();
+      for (int n = 0; n < p.n_terms; ++n) coef.push_back({(R)p.coef[n].real(), (R)p.coef[n].imag()});
+      f.ell_off = (int64_t)ell.size();
+      for (int n = 0; n < p.n_terms; ++n)
+        for (int r = 0; r < kResRank; ++r) ell.push_back(r < p.rank ? (R)p.ell[(size_t)n * p.rank + r] : R(0));
+    }
+  }
+  // Jobs grouped by workgroup size (next power of two >= max(64, Z)), longest first.
+  std::vector<std::vector<ResJob>> groups(5);   // 64, 128, 256, 512, 1024
+  std::vector<std::vector<double>> costs(5);
+  for (int i = 0; i < ns; ++i) {
+    int g = 0;
+    while ((64 << g) < specs[i].Z) ++g;
+    for (int b = 0; b < nB; ++b) {
+      const FieldPlan &p = plans[(size_t)i * nB + b];
+      for (int64_t s = 0; s < M; ++s) {
+        ResJob j;
+        j.sys = i;
+        j.field = i * nB + b;
+        j.sample = (int32_t)s;
+        j.pad = 0;
+        j.out = ((int64_t)idx[i] * nB + b) * M + s;
+        groups[g].push_back(j);
+        costs[g].push_back((double)p.n_steps * p.n_terms);
+      }
+    }
+  }
+  struct Buf {
+    void *p = nullptr;
+    ~Buf() { if (p) (void)hipFree(p); }
+  };
+  Buf bS, bF, bC, bE, bT, bJ, bFl;
+  auto alloc = [&](Buf &b, size_t n) -> int {
+    if (hipMalloc(&b.p, std::max<size_t>(n, 16)) != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(RP_ENOMEM, "hipMalloc failed");
+    }
+    return RP_OK;
+  };
+  int64_t njobs = 0;
+  for (auto &g : groups) njobs += (int64_t)g.size();
+  int rc;
+  if ((rc = alloc(bS, rsys.size() * sizeof(ResSys<R>))) || (rc = alloc(bF, rf.size() * sizeof(ResField<R>))) ||
+      (rc = alloc(bC, coef.size() * sizeof(cx<R>))) || (rc = alloc(bE, ell.size() * sizeof(R))) ||
+      (rc = alloc(bT, tab_elems * sizeof(cx<double>))) || (rc = alloc(bJ, njobs * sizeof(ResJob))) ||
+      (rc = alloc(bFl, 16)))
+    return rc;
+  HIPCHK(hipMemcpyAsync(bS.p, rsys.data(), rsys.size() * sizeof(ResSys<R>), hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(bF.p, rf.data(), rf.size() * sizeof(ResField<R>), hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(bC.p, coef.data(), coef.size() * sizeof(cx<R>), hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(bE.p, ell.data(), ell.size() * sizeof(R), hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemsetAsync(bFl.p, 0, 16, st));
+  for (int i = 0; i < ns; ++i) {
+    const int N = specs[i].N();
+    CohArgs ca;
+    std::memset(&ca, 0, sizeof(ca));
+    ca.angles = angles + aoff[idx[i]];
+    ca.tab = (cx<double> *)bT.p + rsys[i].tab_off;
+    ca.M = M;
+    ca.N = N;
+    ca.mode = op.init_mode;
+    for (int k = 0; k < N; ++k) ca.two_I[k] = specs[i].two_I[k];
+    if (N > 0) hipLaunchKernelGGL(k_coherent, dim3(grid1(M * N)), dim3(256), 0, st, ca);
+  }
+  HIPCHK(hipGetLastError());
+  std::vector<ResJob> all;
+  std::vector<int64_t> start(6, 0);
+  for (int g = 0; g < 5; ++g) {
+    std::vector<size_t> ord(groups[g].size());
+    std::iota(ord.begin(), ord.end(), 0);
+    std::stable_sort(ord.begin(), ord.end(), [&](size_t a, size_t b) { return costs[g][a] > costs[g][b]; });
+    for (size_t q : ord) all.push_back(groups[g][q]);
+    start[g + 1] = (int64_t)all.size();
+  }
+  HIPCHK(hipMemcpyAsync(bJ.p, all.data(), all.size() * sizeof(ResJob), hipMemcpyHostToDevice, st));
+  for (int g = 0; g < 5; ++g) {
+    const int64_t n = start[g + 1] - start[g];
+    if (n == 0) continue;
+    const int Zb = 64 << g;
+    ResArgs<R> ra;
+    ra.sys = (const ResSys<R> *)bS.p;
+    ra.fields = (const ResField<R> *)bF.p;
+    ra.jobs = (const ResJob *)bJ.p + start[g];
+    ra.coef = (const cx<R> *)bC.p;
+    ra.ell = (const R *)bE.p;
+    ra.tab = (const cx<double> *)bT.p;
+    ra.phi = phi;
+    ra.flag = (int *)bFl.p;
+    ra.njobs = n;
+    const size_t shmem = 2 * 4 * (size_t)Zb * sizeof(cx<R>);
+    if (Zb > 512) {
+      HIPCHK(hipFuncSetAttribute((const void *)k_resident<R, 1024, 24>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                 (int)shmem));
+      hipLaunchKernelGGL((k_resident<R, 1024, 24>), dim3((unsigned)n), dim3(Zb), shmem, st, ra);
+    } else {
+      HIPCHK(hipFuncSetAttribute((const void *)k_resident<R, 512, kResRank>,
+                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem));
+      hipLaunchKernelGGL((k_resident<R, 512, kResRank>), dim3((unsigned)n), dim3(Zb), shmem, st, ra);
+    }
+    HIPCHK(hipGetLastError());
+  }
+  int flag = 0;
+  HIPCHK(hipMemcpyAsync(&flag, bFl.p, sizeof(int), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  if (flag) return fail(RP_ENOTCONV, "wavepacket norm grew or became NaN (spectral bound violated)");
+  return RP_OK;
+}
+
 }  // namespace rp
 
 // ============================================================================= C ABI
@@ -1097,7 +1478,7 @@ extern "C" int rp_plan_field(const rp_system *s, double B_mT, const rp_opts *opt
   SystemSpec spec = make_spec(s->n_nuc[0], s->n_nuc[1], s->two_I, s->a_mT, s->J_mT, s->kS, s->kT, s->T_us, g);
   FieldPlan p;
   std::string msg;
-  if (!plan_field(spec, B_mT, op.tol, op.rdt, op.r_scale, op.chol_tol, p, msg)) return fail(RP_EINVAL, msg);
+  if (!plan_field(spec, B_mT, op.tol, op.rdt, op.r_scale, op.chol_tol, op.max_growth, p, msg)) return fail(RP_EINVAL, msg);
   info[0] = p.r;
   info[1] = p.c_re;
   info[2] = p.c_im;
@@ -1169,10 +1550,35 @@ extern "C" int rp_propagate(const rp_system *sys, int32_t n_sys, const double *B
   log.on = (op.flags & RP_FLAG_PROFILE) != 0;
   if (log.on) g_prof = Profile();
   hipEvent_t t0 = log.mark(st);
+  // Systems small enough for the LDS-resident kernel run together in one launch per size class;
+  // the rest use the tiled kernels, one system at a time.
+  std::vector<int64_t> aoffs(n_sys, 0);
+  std::vector<int> resident;
+  {
+    int64_t o = 0;
+    const int64_t zmax = op.precision == 64 ? kResMax64 : kResMax32;
+    for (int i = 0; i < n_sys; ++i) {
+      aoffs[i] = o;
+      const int N = sys[i].n_nuc[0] + sys[i].n_nuc[1];
+      o += M * N * 2;
+      int64_t Z = 1;
+      for (int k = 0; k < N; ++k) Z *= sys[i].two_I[k] + 1;
+      if (!(op.flags & RP_FLAG_TILED) && !log.on && Z <= zmax) resident.push_back(i);
+    }
+  }
+  if (!resident.empty()) {
+    rc = op.precision == 64 ? propagate_resident<double>(resident, sys, B_mT, nB, angles, aoffs, M, op, phi, st)
+                            : propagate_resident<float>(resident, sys, B_mT, nB, angles, aoffs, M, op, phi, st);
+    if (rc) return rc;
+  }
   int64_t aoff = 0;
   for (int i = 0; i < n_sys; ++i) {
     const rp_system *s = &sys[i];
     const int N = s->n_nuc[0] + s->n_nuc[1];
+    if (std::find(resident.begin(), resident.end(), i) != resident.end()) {
+      aoff += M * N * 2;
+      continue;
+    }
     SystemSpec spec = make_spec(s->n_nuc[0], s->n_nuc[1], s->two_I, s->a_mT, s->J_mT, s->kS, s->kT, s->T_us,
                                 gamma_of(s));
     const double *ang = angles ? angles + aoff : nullptr;

@@ -41,6 +41,7 @@ EXPORTS = ["rp_sample", "rp_propagate", "rp_yield", "rp_strerror", "rp_last_erro
            "rp_plan_field", "rp_profile_last", "rp_mlp_param_count", "rp_mlp_workspace_floats",
            "rp_mlp_features", "rp_mlp_forward", "rp_mlp_train_step", "rp_cv_beta"]
 RP_FLAG_PROFILE = 1
+RP_FLAG_TILED = 2
 
 
 def lib():
@@ -132,7 +133,7 @@ def sample(system: SpinSystem, seed, M, first=0, stream_id=0, basis_mode=0, out=
 
 
 def propagate(systems, B_mT, angles, M, precision=64, init_mode=0, tol=0.0, rdt=0.0, r_scale=0.0,
-              workspace_bytes=0, out=None, profile=False):
+              workspace_bytes=0, out=None, profile=False, tiled=False):
     """rp_propagate: single-wavepacket yields [n_sys][nB][M] (float64 CUDA tensor).
 
     ``systems`` is a SpinSystem or a list; ``B_mT`` is [n_sys][nB] (host);
@@ -150,7 +151,8 @@ def propagate(systems, B_mT, angles, M, precision=64, init_mode=0, tol=0.0, rdt=
     if out is None:
         out = torch.empty((len(systems), nB, M), dtype=torch.float64, device="cuda")
     ang = _dev_ptr(angles, torch.float64) if angles is not None and angles.numel() else None
-    o = _opts(precision, init_mode, tol, rdt, r_scale, workspace_bytes, RP_FLAG_PROFILE if profile else 0)
+    o = _opts(precision, init_mode, tol, rdt, r_scale, workspace_bytes,
+              (RP_FLAG_PROFILE if profile else 0) | (RP_FLAG_TILED if tiled else 0))
     _check(lib().rp_propagate(arr, len(cs), B.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), nB, ang, M,
                               ctypes.byref(o), _dev_ptr(out, torch.float64), None, _stream(torch)))
     return out

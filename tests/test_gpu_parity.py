@@ -51,25 +51,28 @@ def test_sampler_bit_exact(mode):
 
 
 # --------------------------------------------------------------------------- tiny workload (Z = 8)
+@pytest.mark.parametrize("tiled", [False, True])
 @pytest.mark.parametrize("prec", [64, 32])
-def test_tiny_workload_parity(prec):
+def test_tiny_workload_parity(prec, tiled):
+    """Both paths: LDS-resident (default for small systems) and the tiled kernels."""
     w = workloads.tiny_c1()
     s = w.systems[0]
-    _say("tiny workload parity, precision", prec)
+    _say("tiny workload parity, precision", prec, "tiled", tiled)
     ang = rp.sample(s, w.seed, w.M)
-    phi = rp.propagate(s, w.fields_mT, ang, w.M, precision=prec).cpu().numpy()[0]
+    phi = rp.propagate(s, w.fields_mT, ang, w.M, precision=prec, tiled=tiled).cpu().numpy()[0]
     want = gc.oracle_phi(s, w.fields_mT[0], philox.sample_angles(w.seed, 0, w.M, s.N))
     assert _rel(phi, want) < TOL[prec]
 
 
+@pytest.mark.parametrize("tiled", [False, True])
 @pytest.mark.parametrize("prec", [64, 32])
-def test_general_spins_exchange_triplet_dissipation(prec):
+def test_general_spins_exchange_triplet_dissipation(prec, tiled):
     """Spin-1 nucleus (mixed radix), J != 0 and kT > kS (P_T is the dissipative projector)."""
     s = SpinSystem(2, 1, [1, 2, 1], [0.8, -0.3, 0.5], J_mT=0.4, kS=0.5, kT=2.0, T_us=3.0)
     B = np.array([[0.0, 1.7, 4.0]])
-    _say("general spins, precision", prec)
+    _say("general spins, precision", prec, "tiled", tiled)
     ang = rp.sample(s, 77, 8)
-    phi = rp.propagate(s, B, ang, 8, precision=prec).cpu().numpy()[0]
+    phi = rp.propagate(s, B, ang, 8, precision=prec, tiled=tiled).cpu().numpy()[0]
     want = gc.oracle_phi(s, B[0], philox.sample_angles(77, 0, 8, 3))
     assert _rel(phi, want) < TOL[prec]
 
@@ -148,11 +151,34 @@ def test_yield_statistics():
     assert np.max(np.abs(m.cpu().numpy() - wm)) < 1e-14 and np.max(np.abs(e.cpu().numpy() - we)) < 1e-14
 
 
-def test_underestimated_spectrum_is_reported():
+@pytest.mark.parametrize("tiled", [False, True])
+def test_underestimated_spectrum_is_reported(tiled):
     w = workloads.tiny_c1()
     s = w.systems[0]
-    _say("notconv")
+    _say("notconv, tiled", tiled)
     ang = rp.sample(s, 1, 2)
     with pytest.raises(rp.RpError) as ei:
-        rp.propagate(s, np.array([[4.0]]), ang, 2, r_scale=0.3)
+        rp.propagate(s, np.array([[4.0]]), ang, 2, r_scale=0.3, tiled=tiled)
     assert ei.value.code == rp.RP_ENOTCONV
+
+
+def test_resident_batch_of_unequal_systems():
+    """Systems of 8, 64, 256 and 1024 nuclear states (spin-1/2 and spin-1 mixes) in one call:
+    the LDS-resident launches agree with the tiled kernels and, for the small ones, the oracle."""
+    rng = np.random.default_rng(11)
+    systems = [SpinSystem(2, 1, [1, 1, 1], [0.8, 0.3, 0.5], kS=1.0, kT=1.0, T_us=4.0),
+               SpinSystem(3, 2, [1, 2, 1, 2, 1], list(rng.uniform(-0.8, 0.8, 5)), J_mT=0.3, kS=0.4, kT=2.2, T_us=3.0),
+               SpinSystem(4, 4, [1] * 8, list(rng.normal(0, 0.7, 8)), kS=2.0, kT=0.5, T_us=3.0),
+               SpinSystem(5, 5, [1] * 10, list(rng.normal(0, 0.7, 10)), kS=0.3, kT=1.1, T_us=2.0)]
+    B = np.array([[0.0, 1.0, 3.0]] * 4)
+    M = 5
+    angs = [rp.sample(s, 40 + i, M) for i, s in enumerate(systems)]
+    cat = torch.cat([a.reshape(-1) for a in angs])
+    for prec in (32, 64):
+        _say("resident batch, precision", prec)
+        res = rp.propagate(systems, B, cat, M, precision=prec).cpu().numpy()
+        til = rp.propagate(systems, B, cat, M, precision=prec, tiled=True).cpu().numpy()
+        assert np.max(np.abs(res - til) / til) < (1e-11 if prec == 64 else 2e-5)
+        for i in (0, 1):
+            want = gc.oracle_phi(systems[i], B[i], philox.sample_angles(40 + i, 0, M, systems[i].N))
+            assert _rel(res[i], want) < TOL[prec]
