@@ -28,13 +28,15 @@ struct cx {
 // Per-system constants in the kernel-argument segment (uniform across the grid).
 template <typename R>
 struct SysArgs {
-  int32_t N, N1, all_half, pad;
+  int32_t N, N1, all_half, nhalf;   // nhalf: leading spin-1/2 nuclei (strides 2^k)
+  int32_t tiled, pad0, pad1, pad2;  // tiled: k_cheb_tile applies (nhalf == N, or nhalf >= 8)
   int64_t Z;
   R J;       // exchange (rad/us): diagonal +-J/2, ab<->ba coupling J
   R beta;    // coefficient of i*beta*P_S in the kernel operator
   int32_t stride[RP_MAX_NUCLEI];
   int32_t d[RP_MAX_NUCLEI];
-  int32_t shift[RP_MAX_NUCLEI];        // log2(stride) for all-spin-1/2 systems
+  int32_t shift[RP_MAX_NUCLEI];        // log2(stride) for the leading spin-1/2 nuclei
+  int32_t rad[RP_MAX_NUCLEI];          // radical (0, 1) of each nucleus
   R a[RP_MAX_NUCLEI];                  // a_k (rad/us), for the diagonal sum a_k m_k
   R f[RP_MAX_NUCLEI][RP_MAX_TWO_I];    // (a_k/2) sqrt(I(I+1) - m(m-1)), link between digits n, n+1
 };

@@ -21,9 +21,25 @@ SystemSpec make_spec(int N1, int N2, const int32_t *two_I, const double *a_mT, d
   for (int k = 0; k < N1 + N2; ++k) {
     s.two_I.push_back(two_I[k]);
     s.a.push_back(a_mT[k] * gamma);
+    s.rad.push_back(k < N1 ? 0 : 1);
+    s.perm.push_back(k);
     s.Z *= (two_I[k] + 1);
   }
   return s;
+}
+
+SystemSpec tile_order(const SystemSpec &s) {
+  std::vector<int> idx(s.N());
+  for (int k = 0; k < s.N(); ++k) idx[k] = k;
+  std::stable_sort(idx.begin(), idx.end(), [&](int x, int y) { return s.two_I[x] < s.two_I[y]; });
+  SystemSpec o = s;
+  for (int k = 0; k < s.N(); ++k) {
+    o.two_I[k] = s.two_I[idx[k]];
+    o.a[k] = s.a[idx[k]];
+    o.rad[k] = s.rad[idx[k]];
+    o.perm[k] = s.perm[idx[k]];
+  }
+  return o;
 }
 
 void bessel_j(double x, int nmax, double *out) {
@@ -172,22 +188,20 @@ static bool radical_extremes(const RadicalOp &op, double &lo, double &hi) {
 
 bool spectral_interval(const SystemSpec &s, double omega, double &Emin, double &Emax) {
   double lo_sum = 0.0, hi_sum = 0.0;
-  int k0 = 0;
   for (int rad = 0; rad < 2; ++rad) {
     RadicalOp op;
-    op.n = rad == 0 ? s.N1 : s.N2;
     op.omega = omega;
     int64_t st = 1;
-    for (int q = 0; q < op.n; ++q) {
-      const int k = k0 + q;
+    for (int k = 0; k < s.N(); ++k) {
+      if (s.rad[k] != rad) continue;
       op.stride.push_back(st);
       op.d.push_back(s.two_I[k] + 1);
       op.a.push_back(s.a[k]);
       op.twoI.push_back(s.two_I[k]);
       st *= s.two_I[k] + 1;
+      ++op.n;
     }
     op.dim = 2 * st;
-    k0 += op.n;
     double lo, hi;
     if (!radical_extremes(op, lo, hi)) return false;
     lo_sum += lo;

@@ -25,6 +25,8 @@ struct SystemSpec {
   int N1 = 0, N2 = 0;
   std::vector<int> two_I;
   std::vector<double> a;       // rad/us
+  std::vector<int> rad;        // radical (0 or 1) of each nucleus
+  std::vector<int> perm;       // caller's index of each nucleus (identity unless reordered)
   double J = 0.0;              // rad/us (term 2 J S1.S2)
   double kS = 0.0, kT = 0.0;   // 1/us
   double T = 0.0;              // us
@@ -51,6 +53,11 @@ struct FieldPlan {
 // Builds the spec from the C-ABI struct fields (validated by the caller).
 SystemSpec make_spec(int N1, int N2, const int32_t *two_I, const double *a_mT, double J_mT,
                      double kS, double kT, double T, double gamma);
+
+// The same system with its nuclei reordered for the tiled kernels: spin-1/2 nuclei first
+// (power-of-two strides), then the others by increasing 2I.  Radical flags and the caller's
+// indices travel with each nucleus; the physics does not depend on the order.
+SystemSpec tile_order(const SystemSpec &s);
 
 // J_0(x)..J_nmax(x), x >= 0, Miller backward recurrence with the normalisation
 // J_0 + 2 sum_k J_2k = 1.

@@ -118,11 +118,12 @@ __global__ __launch_bounds__(256) void k_sample(SampleArgs a) {
 
 // ----------------------------------------------------------------------------- initial wavepacket
 struct CohArgs {
-  const double *angles;   // [M][N][2]
-  cx<double> *tab;        // [M][N][RP_MAX_TWO_I+1]
+  const double *angles;   // [M][N][2], caller's nucleus order
+  cx<double> *tab;        // [M][N][RP_MAX_TWO_I+1], internal nucleus order
   int64_t M;
   int32_t N, mode;
-  int32_t two_I[RP_MAX_NUCLEI];
+  int32_t two_I[RP_MAX_NUCLEI];   // internal order
+  int32_t perm[RP_MAX_NUCLEI];    // caller's index of internal nucleus k
 };
 
 // Components <I, I-n | Omega> of the coherent state of Eq. 15:
@@ -131,10 +132,12 @@ struct CohArgs {
 __global__ __launch_bounds__(256) void k_coherent(CohArgs a) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= a.M * a.N) return;
-  const int k = (int)(i % a.N);
+  const int64_t s = i / a.N;
+  const int k = (int)(i - s * a.N);
   const int t = a.two_I[k];
   cx<double> *out = a.tab + i * (RP_MAX_TWO_I + 1);
-  const double v0 = a.angles[2 * i], v1 = a.angles[2 * i + 1];
+  const int64_t src = s * a.N + a.perm[k];
+  const double v0 = a.angles[2 * src], v1 = a.angles[2 * src + 1];
   if (a.mode == 1) {
     const int dg = (int)v0;
     for (int n = 0; n <= RP_MAX_TWO_I; ++n) out[n] = {n == dg ? 1.0 : 0.0, 0.0};
@@ -289,12 +292,14 @@ __device__ __forceinline__ void finish_term(const TermArgs<R> &ta, const SysArgs
   }
 }
 
-// One Chebyshev term for systems of spin-1/2 nuclei with strides 2^k.  The workgroup's
-// 256 nuclear indices form a tile that holds every partner along the fast axes
-// (stride < 256); the tile is staged in LDS and those partners are read from it.
-// Partners along the slow axes are read from global memory in batches of 8 loads.
+// One Chebyshev term for systems whose nuclei are ordered spin-1/2 first (strides 2^k) and
+// whose higher spins, if any, have strides that are multiples of 256.  The workgroup's 256
+// nuclear indices form a tile that holds every partner along the fast axes (stride < 256);
+// the tile is staged in LDS and those partners are read from it.  Partners along the slow
+// spin-1/2 axes are read from global memory in batches of 8 loads; higher spins follow with
+// workgroup-uniform digits.
 template <typename R, int MODE>
-__global__ __launch_bounds__(256) void k_cheb_half(TermArgs<R> ta, SysArgs<R> sa) {
+__global__ __launch_bounds__(256) void k_cheb_tile(TermArgs<R> ta, SysArgs<R> sa) {
   __shared__ cx<R> tile[kBlock * 4];
   __shared__ double lds[4];
   const int64_t total = (int64_t)ta.njobs * ta.nbx;
@@ -331,13 +336,14 @@ __global__ __launch_bounds__(256) void k_cheb_half(TermArgs<R> ta, SysArgs<R> sa
   if (live) {
     cx<R> y0 = zero, y1 = zero, y2 = zero, y3 = zero;
     R h1 = R(0), h2 = R(0);
-    const int kf = sa.N < 8 ? sa.N : 8;   // nuclei whose partners lie in the tile
+    const int nh = sa.nhalf;
+    const int kf = nh < 8 ? nh : 8;   // spin-1/2 nuclei whose partners lie in the tile
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
       if (k < kf) {
         const int bit = (tid >> k) & 1;
         const int pt = tid ^ (1 << k);
-        const bool r1 = k < sa.N1;
+        const bool r1 = sa.rad[k] == 0;
         const R mk = bit ? R(-0.5) : R(0.5);
         if (r1) h1 += sa.a[k] * mk; else h2 += sa.a[k] * mk;
         cx<R> p0, p1;
@@ -351,16 +357,17 @@ __global__ __launch_bounds__(256) void k_cheb_half(TermArgs<R> ta, SysArgs<R> sa
         flip_half(r1, bit, sa.f[k][0], p0, p1, y0, y1, y2, y3);
       }
     }
-    for (int k0 = kf; k0 < sa.N; k0 += 8) {
+    for (int k0 = kf; k0 < nh; k0 += 8) {
       cx<R> pa[8], pb[8];
 #pragma unroll
       for (int j = 0; j < 8; ++j) {
         const int k = k0 + j;
-        if (k < sa.N) {
+        if (k < nh) {
           const int bit = (int)((M >> k) & 1);
           const int64_t P = M ^ ((int64_t)1 << k);
           // slow axis: every lane of a wave has the same bit, so both loads are coalesced
-          const int c0 = k < sa.N1 ? 2 * bit : bit, c1 = k < sa.N1 ? 2 * bit + 1 : bit + 2;
+          const bool r1k = sa.rad[k] == 0;
+          const int c0 = r1k ? 2 * bit : bit, c1 = r1k ? 2 * bit + 1 : bit + 2;
           pa[j] = X[c0 * Z + P];
           pb[j] = X[c1 * Z + P];
         }
@@ -368,12 +375,65 @@ __global__ __launch_bounds__(256) void k_cheb_half(TermArgs<R> ta, SysArgs<R> sa
 #pragma unroll
       for (int j = 0; j < 8; ++j) {
         const int k = k0 + j;
-        if (k < sa.N) {
+        if (k < nh) {
           const int bit = (int)((M >> k) & 1);
-          const bool r1 = k < sa.N1;
+          const bool r1 = sa.rad[k] == 0;
           const R mk = bit ? R(-0.5) : R(0.5);
           if (r1) h1 += sa.a[k] * mk; else h2 += sa.a[k] * mk;
           flip_half(r1, bit, sa.f[k][0], pa[j], pb[j], y0, y1, y2, y3);
+        }
+      }
+    }
+    // Higher spins come last, with strides that are multiples of the 256-index tile: their
+    // digits are the same for the whole workgroup.  A missing partner (digit at the edge) gets
+    // coefficient 0 and reads this thread's own index, so all loads of a batch of four nuclei
+    // are in bounds and are issued together, each a unit-stride load.
+    int64_t rem = (bx * kBlock) >> nh;
+    for (int k0 = nh; k0 < sa.N; k0 += 4) {
+      cx<R> pm0[4], pm1[4], pp0[4], pp1[4];
+      R fm[4], fpl[4];
+      bool r1v[4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int k = k0 + j;
+        fm[j] = R(0);
+        fpl[j] = R(0);
+        r1v[j] = true;
+        if (k < sa.N) {
+          const int dk = sa.d[k];
+          const int64_t q = rem / dk;
+          const int n = __builtin_amdgcn_readfirstlane((int)(rem - q * dk));
+          rem = q;
+          const int64_t st = sa.stride[k];
+          const bool r1 = sa.rad[k] == 0;
+          r1v[j] = r1;
+          const R mk = R(0.5) * R(dk - 1) - R(n);
+          if (r1) h1 += sa.a[k] * mk; else h2 += sa.a[k] * mk;
+          const int64_t Pm = n > 0 ? M - st : M, Pp = n < dk - 1 ? M + st : M;
+          fm[j] = n > 0 ? sa.f[k][n - 1] : R(0);
+          fpl[j] = n < dk - 1 ? sa.f[k][n] : R(0);
+          // minus partner (digit n-1) feeds the alpha components from beta ones; plus partner
+          // (digit n+1) feeds beta components from alpha ones
+          pm0[j] = X[(r1 ? 2 : 1) * Z + Pm];
+          pm1[j] = X[3 * Z + Pm];
+          pp0[j] = X[Pp];
+          pp1[j] = X[(r1 ? 1 : 2) * Z + Pp];
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        if (k0 + j < sa.N) {
+          if (r1v[j]) {
+            y0 = cadd(y0, cscale(fm[j], pm0[j]));
+            y1 = cadd(y1, cscale(fm[j], pm1[j]));
+            y2 = cadd(y2, cscale(fpl[j], pp0[j]));
+            y3 = cadd(y3, cscale(fpl[j], pp1[j]));
+          } else {
+            y0 = cadd(y0, cscale(fm[j], pm0[j]));
+            y2 = cadd(y2, cscale(fm[j], pm1[j]));
+            y1 = cadd(y1, cscale(fpl[j], pp0[j]));
+            y3 = cadd(y3, cscale(fpl[j], pp1[j]));
+          }
         }
       }
     }
@@ -423,7 +483,7 @@ __global__ __launch_bounds__(256) void k_cheb_gen(TermArgs<R> ta, SysArgs<R> sa)
       const int n = (int)(rem - q * dk);
       rem = q;
       const R mk = R(0.5) * R(dk - 1) - R(n);
-      const bool r1 = k < sa.N1;
+      const bool r1 = sa.rad[k] == 0;
       if (r1) h1 += sa.a[k] * mk; else h2 += sa.a[k] * mk;
       if (n > 0) {        // partner digit n-1: beta component -> alpha component (I- S+)
         const R fk = sa.f[k][n - 1];
@@ -634,7 +694,7 @@ __global__ __launch_bounds__(MAXB) void k_resident(ResArgs<R> ra) {
           const int nd = rem % dk;
           rem /= dk;
           const R mk = R(0.5) * R(dk - 1) - R(nd);
-          const bool r1 = k < sa.N1;
+          const bool r1 = sa.rad[k] == 0;
           if (r1) h1 += sa.a[k] * mk; else h2 += sa.a[k] * mk;
           if (nd > 0) {        // partner digit n-1: beta component -> alpha component
             const R f = sa.f[k][nd - 1];
@@ -955,10 +1015,14 @@ static SysArgs<R> make_sysargs(const SystemSpec &s) {
   // i beta P_S reproduces -i (dk/2) P_x together with the shift (see plan.hpp).
   a.beta = (R)(s.kS >= s.kT ? -0.5 * (s.kS - s.kT) : 0.5 * (s.kT - s.kS));
   a.all_half = 1;
+  a.nhalf = 0;
+  while (a.nhalf < a.N && s.two_I[a.nhalf] == 1) ++a.nhalf;
+  a.tiled = (a.nhalf == a.N || a.nhalf >= 8) ? 1 : 0;
   int64_t st = 1;
   for (int k = 0; k < a.N; ++k) {
     a.stride[k] = (int32_t)st;
     a.d[k] = s.two_I[k] + 1;
+    a.rad[k] = s.rad[k];
     if (s.two_I[k] != 1) a.all_half = 0;
     int sh = 0;
     while ((int64_t(1) << sh) < st) ++sh;
@@ -1112,7 +1176,10 @@ static int propagate_system(const SystemSpec &spec, const double *B, int nB, con
     ca.M = M;
     ca.N = N;
     ca.mode = op.init_mode;
-    for (int k = 0; k < N; ++k) ca.two_I[k] = spec.two_I[k];
+    for (int k = 0; k < N; ++k) {
+      ca.two_I[k] = spec.two_I[k];
+      ca.perm[k] = spec.perm[k];
+    }
     hipLaunchKernelGGL(k_coherent, dim3(grid1(M * N)), dim3(256), 0, st, ca);
     HIPCHK(hipGetLastError());
   }
@@ -1179,8 +1246,8 @@ static int propagate_system(const SystemSpec &spec, const double *B, int nB, con
       ta.dfirst = D;
       const double eb = (double)sizeof(R) / 4.0;   // bytes per element, in units of complex-FP32 bytes
       log.mark(st);
-      if (sa.all_half)
-        hipLaunchKernelGGL((k_cheb_half<R, kFirst>), dim3(grid), dim3(kBlock), 0, st, ta, sa);
+      if (sa.tiled)
+        hipLaunchKernelGGL((k_cheb_tile<R, kFirst>), dim3(grid), dim3(kBlock), 0, st, ta, sa);
       else
         hipLaunchKernelGGL((k_cheb_gen<R, kFirst>), dim3(grid), dim3(kBlock), 0, st, ta, sa);
       double bytes = 28.0 * eb;
@@ -1192,11 +1259,11 @@ static int propagate_system(const SystemSpec &spec, const double *B, int nB, con
         ta.n = n;
         ta.dnext = D + (int64_t)(n + 1) * slab;
         const bool acc3 = (n % 3) == 0;
-        if (sa.all_half) {
+        if (sa.tiled) {
           if (acc3)
-            hipLaunchKernelGGL((k_cheb_half<R, kAcc3>), dim3(grid), dim3(kBlock), 0, st, ta, sa);
+            hipLaunchKernelGGL((k_cheb_tile<R, kAcc3>), dim3(grid), dim3(kBlock), 0, st, ta, sa);
           else
-            hipLaunchKernelGGL((k_cheb_half<R, kPlain>), dim3(grid), dim3(kBlock), 0, st, ta, sa);
+            hipLaunchKernelGGL((k_cheb_tile<R, kPlain>), dim3(grid), dim3(kBlock), 0, st, ta, sa);
         } else {
           if (acc3)
             hipLaunchKernelGGL((k_cheb_gen<R, kAcc3>), dim3(grid), dim3(kBlock), 0, st, ta, sa);
@@ -1273,8 +1340,8 @@ static int propagate_resident(const std::vector<int> &idx, const rp_system *sys,
   const int ns = (int)idx.size();
   std::vector<SystemSpec> specs;
   for (int i : idx)
-    specs.push_back(make_spec(sys[i].n_nuc[0], sys[i].n_nuc[1], sys[i].two_I, sys[i].a_mT, sys[i].J_mT, sys[i].kS,
-                              sys[i].kT, sys[i].T_us, gamma_of(&sys[i])));
+    specs.push_back(tile_order(make_spec(sys[i].n_nuc[0], sys[i].n_nuc[1], sys[i].two_I, sys[i].a_mT, sys[i].J_mT,
+                                         sys[i].kS, sys[i].kT, sys[i].T_us, gamma_of(&sys[i]))));
   // Plan every (system, field) with a step short enough that the quadrature rank fits kResRank.
   std::vector<FieldPlan> plans((size_t)ns * nB);
   std::vector<std::string> msgs((size_t)ns * nB);
@@ -1394,7 +1461,10 @@ static int propagate_resident(const std::vector<int> &idx, const rp_system *sys,
     ca.M = M;
     ca.N = N;
     ca.mode = op.init_mode;
-    for (int k = 0; k < N; ++k) ca.two_I[k] = specs[i].two_I[k];
+    for (int k = 0; k < N; ++k) {
+      ca.two_I[k] = specs[i].two_I[k];
+      ca.perm[k] = specs[i].perm[k];
+    }
     if (N > 0) hipLaunchKernelGGL(k_coherent, dim3(grid1(M * N)), dim3(256), 0, st, ca);
   }
   HIPCHK(hipGetLastError());
@@ -1579,8 +1649,8 @@ extern "C" int rp_propagate(const rp_system *sys, int32_t n_sys, const double *B
       aoff += M * N * 2;
       continue;
     }
-    SystemSpec spec = make_spec(s->n_nuc[0], s->n_nuc[1], s->two_I, s->a_mT, s->J_mT, s->kS, s->kT, s->T_us,
-                                gamma_of(s));
+    SystemSpec spec = tile_order(make_spec(s->n_nuc[0], s->n_nuc[1], s->two_I, s->a_mT, s->J_mT, s->kS, s->kT,
+                                           s->T_us, gamma_of(s)));
     const double *ang = angles ? angles + aoff : nullptr;
     double *out = phi + (int64_t)i * nB * M;
     rc = op.precision == 64 ? propagate_system<double>(spec, B_mT + (int64_t)i * nB, nB, ang, M, op, out, st, log)

@@ -113,6 +113,21 @@ def test_multi_block_ragged_mixed_radix():
         assert _rel(phi, want) < TOL[prec] * (10 if prec == 64 else 1)
 
 
+def test_reordered_axes_spin1_first():
+    """Spin-1 nuclei first in the caller's order (one per radical): the library reorders the
+    axes internally (spin-1/2 first) for the tiled kernel; Z = 9 * 2^8 = 2304."""
+    rng = np.random.default_rng(6)
+    a = list(rng.uniform(-0.4, 0.4, 10))
+    s = SpinSystem(5, 5, [2, 1, 1, 1, 1, 2, 1, 1, 1, 1], a, J_mT=-0.2, kS=0.6, kT=1.4, T_us=0.5)
+    B = np.array([[0.5, 3.0]])
+    _say("reordered axes, Z =", s.Z)
+    ang = rp.sample(s, 12, 3)
+    want = gc.oracle_phi_sparse(s, B[0], philox.sample_angles(12, 0, 3, s.N))
+    for prec in (64, 32):
+        phi = rp.propagate(s, B, ang, 3, precision=prec).cpu().numpy()[0]
+        assert _rel(phi, want) < TOL[prec] * (10 if prec == 64 else 1)
+
+
 # --------------------------------------------------------------------------- batching and chunking
 def test_multi_system_call_and_chunking_are_consistent():
     w = workloads.tiny_c1()
