@@ -64,7 +64,7 @@ struct TermArgs {
   int32_t njobs;
   int32_t n;               // producing phi_{n+1}
   int32_t n_terms;
-  int32_t pad;
+  int32_t remap;           // 1: each XCD takes a contiguous range of workgroups (see xcd_remap)
 };
 
 template <typename R>
@@ -79,7 +79,7 @@ struct QuadArgs {
   int32_t njobs;
   int32_t n_terms;
   int32_t rank_pad;
-  int32_t pad;
+  int32_t remap;
 };
 
 struct FinArgs {

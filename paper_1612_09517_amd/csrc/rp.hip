@@ -15,10 +15,12 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <numeric>
 #include <string>
 #include <thread>
+#include <type_traits>
 #include <vector>
 
 #include "kernels.hpp"
@@ -303,7 +305,7 @@ __global__ __launch_bounds__(256) void k_cheb_tile(TermArgs<R> ta, SysArgs<R> sa
   __shared__ cx<R> tile[kBlock * 4];
   __shared__ double lds[4];
   const int64_t total = (int64_t)ta.njobs * ta.nbx;
-  const int64_t L = xcd_remap(blockIdx.x, total);
+  const int64_t L = ta.remap ? xcd_remap(blockIdx.x, total) : (int64_t)blockIdx.x;
   const int64_t job = L / ta.nbx, bx = L - job * ta.nbx;
   const int tid = threadIdx.x;
   const int64_t M = bx * kBlock + tid;
@@ -453,7 +455,7 @@ template <typename R, int MODE>
 __global__ __launch_bounds__(256) void k_cheb_gen(TermArgs<R> ta, SysArgs<R> sa) {
   __shared__ double lds[4];
   const int64_t total = (int64_t)ta.njobs * ta.nbx;
-  const int64_t L = xcd_remap(blockIdx.x, total);
+  const int64_t L = ta.remap ? xcd_remap(blockIdx.x, total) : (int64_t)blockIdx.x;
   const int64_t job = L / ta.nbx, bx = L - job * ta.nbx;
   const int64_t M = bx * kBlock + threadIdx.x;
   const bool live = M < sa.Z;
@@ -531,7 +533,7 @@ template <typename R, int RC>
 __global__ __launch_bounds__(256) void k_quad(QuadArgs<R> qa) {
   __shared__ double lds[4];
   const int64_t total = (int64_t)qa.njobs * qa.nbx;
-  const int64_t L = xcd_remap(blockIdx.x, total);
+  const int64_t L = qa.remap ? xcd_remap(blockIdx.x, total) : (int64_t)blockIdx.x;
   const int64_t job = L / qa.nbx, bx = L - job * qa.nbx;
   const int64_t M = bx * kBlock + threadIdx.x;
   const bool live = M < qa.Z;
@@ -1185,6 +1187,11 @@ static int propagate_system(const SystemSpec &spec, const double *B, int nB, con
   }
   const SysArgs<R> sa = make_sysargs<R>(spec);
   const double kmin = std::min(spec.kS, spec.kT);
+  // Block order: a wavepacket that fits an XCD's 4 MB L2 comfortably is given to one XCD
+  // (its partner tiles stay in that L2); larger ones are spread over all XCDs, so that the
+  // whole GPU works on few wavepackets at a time and far partners hit the Infinity Cache.
+  int remap = vec_bytes <= ((int64_t)1 << 20) ? 1 : 0;
+  if (const char *e = std::getenv("RP_XCD_REMAP")) remap = std::atoi(e);
   const double rtol = op.precision == 64 ? 1e-9 : 1e-4;
 
   cx<R> *bufs[3] = {(cx<R> *)bP0.p, (cx<R> *)bP1.p, (cx<R> *)bP2.p};
@@ -1234,6 +1241,7 @@ static int propagate_system(const SystemSpec &spec, const double *B, int nB, con
       ta.nbx = nbx;
       ta.njobs = (int32_t)active;
       ta.n_terms = nt;
+      ta.remap = remap;
       ta.acc = bufs[ia_];
       cx<R> *even = bufs[ip], *odd = bufs[iodd];
       cx<R> *D = (cx<R> *)bD.p;
@@ -1294,6 +1302,7 @@ static int propagate_system(const SystemSpec &spec, const double *B, int nB, con
       qa.njobs = (int32_t)active;
       qa.n_terms = nt;
       qa.rank_pad = rkp;
+      qa.remap = remap;
       log.mark(st);
       launch_quad<R>(rcw, grid, st, qa);
       log.mark(st);
