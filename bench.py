@@ -220,6 +220,8 @@ def main():
     ap.add_argument("--fields", type=int, default=64)
     ap.add_argument("--precision", type=int, default=32, choices=[32, 64])
     ap.add_argument("--rdt", type=float, default=0.0)
+    ap.add_argument("--autotune", action="store_true",
+                    help="pick r*dt and the XCD workgroup order by timed probes (cached) before timing")
     ap.add_argument("--workspace-gb", type=float, default=0.0,
                     help="device workspace cap per call (bounds how many wavepackets run together)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -274,10 +276,15 @@ def main():
     torch.cuda.set_device(dev)
     stream = torch.cuda.current_stream()
 
+    tuned = {"rdt": args.rdt, "xcd": None}
+    if args.autotune:
+        from paper_1612_09517_amd import autotune
+        tuned = autotune.tune(s, B[0], precision=args.precision)
+
     def step(i, profile=False):
         ang = rp.sample(s, w.seed, Mb, first=i * Mb)
-        phi = rp.propagate(s, B, ang, Mb, precision=args.precision, rdt=args.rdt, profile=profile,
-                           workspace_bytes=int(args.workspace_gb * 2 ** 30))
+        phi = rp.propagate(s, B, ang, Mb, precision=args.precision, rdt=tuned["rdt"], xcd=tuned["xcd"],
+                           profile=profile, workspace_bytes=int(args.workspace_gb * 2 ** 30))
         mean, err = rp.yield_stats(phi[0])
         return phi, mean, err
 
@@ -320,7 +327,9 @@ def main():
         "config": {"workload": "c2_7+7_Z16384: 7+7 spin-1/2, a~U(-1,1) mT, kS=2, kT=0.5 /us, T=20 us, "
                                f"{B.shape[1]} fields 0..10 mT x {Mb} samples per step",
                    "Z": s.Z, "dim": s.dim, "fields": int(B.shape[1]), "samples_per_step": Mb,
-                   "precision": f"complex-FP{args.precision} state, FP64 coefficients and reductions"},
+                   "precision": f"complex-FP{args.precision} state, FP64 coefficients and reductions",
+                   "launch": {"rdt": tuned["rdt"] or 80.0, "xcd": tuned["xcd"] or "default",
+                              "autotuned": bool(args.autotune)}},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": achieved / PEAK_HBM_GBS,
                      "traffic": measured_traffic(args.precision, int(nterms),

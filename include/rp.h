@@ -85,6 +85,15 @@ typedef struct rp_opts {
    workgroup per wavepacket for the whole propagation, every such job of the call in one
    launch per workgroup size.  Profiled calls always use the tiled kernels. */
 #define RP_FLAG_TILED 2
+/* opts->flags: workgroup order of the tiled kernels.  By default a wavepacket of at most 1 MB
+   goes to one XCD (its partner tiles stay in that XCD's L2) and larger ones are spread over
+   all XCDs; these flags force one or the other (for tuning). */
+#define RP_FLAG_XCD_LOCAL 4
+#define RP_FLAG_XCD_SPREAD 8
+/* opts->flags: launch the tiled kernels directly instead of replaying one captured HIP graph
+   per step (graphs are captured per number of active wavepackets and buffer parity, on a
+   stream of the library's own when the caller passes the legacy default stream). */
+#define RP_FLAG_NO_GRAPH 16
 
 /*
  * rp_sample -- directions of the nuclear coherent states (Eq. 18: uniform on

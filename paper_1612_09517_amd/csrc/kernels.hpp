@@ -90,9 +90,10 @@ struct FinArgs {
   int *flag;
   const int32_t *job_field;
   const double *dt;        // [fields]
+  int32_t *stepc;          // [jobs] steps finalised so far (read, then incremented)
   int64_t nbx;
   int32_t njobs;
-  int32_t step;
+  int32_t pad;
   double kS, kmin, rtol;
 };
 

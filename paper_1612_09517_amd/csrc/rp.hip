@@ -17,6 +17,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <map>
 #include <numeric>
 #include <string>
 #include <thread>
@@ -804,7 +805,9 @@ __global__ __launch_bounds__(256) void k_finalize(FinArgs fa) {
     nrm += fa.part_norm[job * fa.nbx + b];
   }
   const int fi = fa.job_field[job];
-  const double decay = exp(-fa.kmin * fa.step * fa.dt[fi]);
+  const int32_t step = fa.stepc[job];
+  fa.stepc[job] = step + 1;
+  const double decay = exp(-fa.kmin * step * fa.dt[fi]);
   fa.phi[job] += fa.kS * decay * y;
   const double Nt = decay * nrm;           // population N(t_j) of the wavepacket
   if (!(Nt <= fa.prev_norm[job] * (1.0 + fa.rtol) + 1e-300) || !(y == y)) atomicOr(fa.flag, 1);
@@ -972,7 +975,9 @@ static int read_opts(const rp_opts *o, Opts &out) {
     out.init_mode = o->init_mode;
     if (o->tol < 0 || o->rdt < 0 || o->r_scale < 0 || o->workspace_bytes < 0)
       return fail(RP_EINVAL, "negative option");
-    if ((o->flags & ~(RP_FLAG_PROFILE | RP_FLAG_TILED)) != 0 || o->reserved != 0)
+    if ((o->flags & ~(RP_FLAG_PROFILE | RP_FLAG_TILED | RP_FLAG_XCD_LOCAL | RP_FLAG_XCD_SPREAD | RP_FLAG_NO_GRAPH)) !=
+            0 ||
+        o->reserved != 0)
       return fail(RP_EINVAL, "unknown flags or nonzero reserved field");
     out.flags = o->flags;
     if (o->tol > 0) out.tol = o->tol;
@@ -1129,7 +1134,7 @@ static int propagate_system(const SystemSpec &spec, const double *B, int nB, con
     void *p = nullptr;
     ~Buf() { if (p) (void)hipFree(p); }
   };
-  Buf bP0, bP1, bP2, bD, bPn, bPq, bPhi, bPrev, bFlag, bFd, bCoef, bEll, bDt, bJf, bJs, bDst, bTab, bOut;
+  Buf bP0, bP1, bP2, bD, bPn, bPq, bPhi, bPrev, bFlag, bFd, bCoef, bEll, bDt, bJf, bJs, bDst, bTab, bOut, bStep;
   auto alloc = [&](Buf &b, size_t bytes) -> int {
     if (hipMalloc(&b.p, std::max<size_t>(bytes, 16)) != hipSuccess) {
       (void)hipGetLastError();
@@ -1150,6 +1155,7 @@ static int propagate_system(const SystemSpec &spec, const double *B, int nB, con
   ALLOC(bPq, chunk * nbx * 16);
   ALLOC(bPhi, chunk * 8);
   ALLOC(bPrev, chunk * 8);
+  ALLOC(bStep, chunk * 4);
   ALLOC(bFlag, 16);
   ALLOC(bFd, nB * sizeof(FieldDev<R>));
   ALLOC(bCoef, coef.size() * sizeof(cx<R>));
@@ -1191,8 +1197,11 @@ static int propagate_system(const SystemSpec &spec, const double *B, int nB, con
   // (its partner tiles stay in that L2); larger ones are spread over all XCDs, so that the
   // whole GPU works on few wavepackets at a time and far partners hit the Infinity Cache.
   int remap = vec_bytes <= ((int64_t)1 << 20) ? 1 : 0;
-  if (const char *e = std::getenv("RP_XCD_REMAP")) remap = std::atoi(e);
+  if (op.flags & RP_FLAG_XCD_LOCAL) remap = 1;
+  if (op.flags & RP_FLAG_XCD_SPREAD) remap = 0;
   const double rtol = op.precision == 64 ? 1e-9 : 1e-4;
+  // Graph replay of the step launches (not while profiling: the events are per launch).
+  const bool use_graph = !log.on && !(op.flags & RP_FLAG_NO_GRAPH);
 
   cx<R> *bufs[3] = {(cx<R> *)bP0.p, (cx<R> *)bP1.p, (cx<R> *)bP2.p};
   for (int64_t j0 = 0; j0 < total_jobs; j0 += chunk) {
@@ -1223,14 +1232,12 @@ static int propagate_system(const SystemSpec &spec, const double *B, int nB, con
     hipLaunchKernelGGL(k_fill, dim3(grid1(nj)), dim3(256), 0, st, (double *)bPhi.p, nj, 0.0);
     hipLaunchKernelGGL(k_fill, dim3(grid1(nj)), dim3(256), 0, st, (double *)bPrev.p, nj, 1.0 + 1e-6);
     HIPCHK(hipGetLastError());
+    HIPCHK(hipMemsetAsync(bStep.p, 0, nj * 4, st));
     int ip = 0, ia_ = 2, iodd = 1;   // psi, accumulator and odd-term buffers
-    const int64_t steps_max = nsteps[job_field[j0]];
-    for (int64_t t = 0; t < steps_max; ++t) {
-      // Jobs of fields with more than t steps form the prefix [0, C(t)) of the sorted list.
-      int64_t nf = 0;
-      while (nf < nB && nsteps[nf] > t) ++nf;
-      const int64_t active = std::min<int64_t>(nj, std::max<int64_t>(0, nf * M - j0));
-      if (active <= 0) break;
+    const int64_t slab = nj * Z;
+    cx<R> *D = (cx<R> *)bD.p;
+    // All launches of one step: Chebyshev terms, in-step quadrature, finalisation.
+    auto enqueue_step = [&](int64_t active, int ipsi, int iacc) {
       const unsigned grid = (unsigned)(active * nbx);
       TermArgs<R> ta;
       std::memset(&ta, 0, sizeof(ta));
@@ -1242,10 +1249,8 @@ static int propagate_system(const SystemSpec &spec, const double *B, int nB, con
       ta.njobs = (int32_t)active;
       ta.n_terms = nt;
       ta.remap = remap;
-      ta.acc = bufs[ia_];
-      cx<R> *even = bufs[ip], *odd = bufs[iodd];
-      cx<R> *D = (cx<R> *)bD.p;
-      const int64_t slab = nj * Z;
+      ta.acc = bufs[iacc];
+      cx<R> *even = bufs[ipsi], *odd = bufs[iodd];
       // n = 0: phi_1 = Gh phi_0
       ta.phin = even;
       ta.phio = odd;
@@ -1289,7 +1294,6 @@ static int propagate_system(const SystemSpec &spec, const double *B, int nB, con
         g_prof.quad_launches += 1;
         g_prof.terms = nt;
       }
-      HIPCHK(hipGetLastError());
       QuadArgs<R> qa;
       std::memset(&qa, 0, sizeof(qa));
       qa.d = D;
@@ -1308,6 +1312,7 @@ static int propagate_system(const SystemSpec &spec, const double *B, int nB, con
       log.mark(st);
       log.close(1);
       FinArgs fa;
+      std::memset(&fa, 0, sizeof(fa));
       fa.part_q = (const double *)bPq.p;
       fa.part_norm = (const double *)bPn.p;
       fa.phi = (double *)bPhi.p;
@@ -1315,14 +1320,47 @@ static int propagate_system(const SystemSpec &spec, const double *B, int nB, con
       fa.flag = (int *)bFlag.p;
       fa.job_field = jf;
       fa.dt = (const double *)bDt.p;
+      fa.stepc = (int32_t *)bStep.p;
       fa.nbx = nbx;
       fa.njobs = (int32_t)active;
-      fa.step = (int32_t)t;
       fa.kS = spec.kS;
       fa.kmin = kmin;
       fa.rtol = rtol;
       hipLaunchKernelGGL(k_finalize, dim3(grid1(active)), dim3(256), 0, st, fa);
-      HIPCHK(hipGetLastError());
+    };
+    // One captured graph per (active jobs, buffer parity) of this chunk, replayed every step.
+    std::map<std::pair<int64_t, int>, hipGraphExec_t> graphs;
+    struct GraphsGuard {
+      std::map<std::pair<int64_t, int>, hipGraphExec_t> &g;
+      ~GraphsGuard() { for (auto &kv : g) (void)hipGraphExecDestroy(kv.second); }
+    } graphs_guard{graphs};
+    const int64_t steps_max = nsteps[job_field[j0]];
+    for (int64_t t = 0; t < steps_max; ++t) {
+      // Jobs of fields with more than t steps form the prefix [0, C(t)) of the sorted list.
+      int64_t nf = 0;
+      while (nf < nB && nsteps[nf] > t) ++nf;
+      const int64_t active = std::min<int64_t>(nj, std::max<int64_t>(0, nf * M - j0));
+      if (active <= 0) break;
+      if (use_graph) {
+        const auto key = std::make_pair(active, ip);
+        auto it = graphs.find(key);
+        if (it == graphs.end()) {
+          HIPCHK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+          enqueue_step(active, ip, ia_);
+          hipGraph_t g = nullptr;
+          const hipError_t ec = hipStreamEndCapture(st, &g);
+          if (ec != hipSuccess || !g) return fail(RP_EDEVICE, std::string("graph capture: ") + hipGetErrorString(ec));
+          hipGraphExec_t ge = nullptr;
+          const hipError_t ei = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
+          (void)hipGraphDestroy(g);
+          if (ei != hipSuccess) return fail(RP_EDEVICE, std::string("graph instantiate: ") + hipGetErrorString(ei));
+          it = graphs.emplace(key, ge).first;
+        }
+        HIPCHK(hipGraphLaunch(it->second, st));
+      } else {
+        enqueue_step(active, ip, ia_);
+        HIPCHK(hipGetLastError());
+      }
       std::swap(ip, ia_);
     }
     hipLaunchKernelGGL(k_scatter, dim3(grid1(nj)), dim3(256), 0, st, (const double *)bPhi.p,
@@ -1625,6 +1663,17 @@ extern "C" int rp_propagate(const rp_system *sys, int32_t n_sys, const double *B
   for (int64_t i = 0; i < (int64_t)n_sys * nB; ++i)
     if (!std::isfinite(B_mT[i])) return fail(RP_EINVAL, "non-finite field");
   hipStream_t st = (hipStream_t)hip_stream;
+  // The legacy default stream cannot be captured into a graph: run the call on a blocking
+  // stream of its own (implicitly ordered with the default stream; the call synchronises
+  // before returning, so its results are ready either way).
+  struct OwnStream {
+    hipStream_t s = nullptr;
+    ~OwnStream() { if (s) { (void)hipStreamSynchronize(s); (void)hipStreamDestroy(s); } }
+  } own;
+  if (!st) {
+    HIPCHK(hipStreamCreate(&own.s));
+    st = own.s;
+  }
   EventLog log;
   log.on = (op.flags & RP_FLAG_PROFILE) != 0;
   if (log.on) g_prof = Profile();

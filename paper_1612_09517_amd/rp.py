@@ -42,6 +42,9 @@ EXPORTS = ["rp_sample", "rp_propagate", "rp_yield", "rp_strerror", "rp_last_erro
            "rp_mlp_features", "rp_mlp_forward", "rp_mlp_train_step", "rp_cv_beta"]
 RP_FLAG_PROFILE = 1
 RP_FLAG_TILED = 2
+RP_FLAG_XCD_LOCAL = 4
+RP_FLAG_XCD_SPREAD = 8
+RP_FLAG_NO_GRAPH = 16
 
 
 def lib():
@@ -133,7 +136,7 @@ def sample(system: SpinSystem, seed, M, first=0, stream_id=0, basis_mode=0, out=
 
 
 def propagate(systems, B_mT, angles, M, precision=64, init_mode=0, tol=0.0, rdt=0.0, r_scale=0.0,
-              workspace_bytes=0, out=None, profile=False, tiled=False):
+              workspace_bytes=0, out=None, profile=False, tiled=False, xcd=None, graph=True):
     """rp_propagate: single-wavepacket yields [n_sys][nB][M] (float64 CUDA tensor).
 
     ``systems`` is a SpinSystem or a list; ``B_mT`` is [n_sys][nB] (host);
@@ -151,8 +154,13 @@ def propagate(systems, B_mT, angles, M, precision=64, init_mode=0, tol=0.0, rdt=
     if out is None:
         out = torch.empty((len(systems), nB, M), dtype=torch.float64, device="cuda")
     ang = _dev_ptr(angles, torch.float64) if angles is not None and angles.numel() else None
-    o = _opts(precision, init_mode, tol, rdt, r_scale, workspace_bytes,
-              (RP_FLAG_PROFILE if profile else 0) | (RP_FLAG_TILED if tiled else 0))
+    flags = (RP_FLAG_PROFILE if profile else 0) | (RP_FLAG_TILED if tiled else 0)
+    flags |= 0 if graph else RP_FLAG_NO_GRAPH
+    if xcd == "local":
+        flags |= RP_FLAG_XCD_LOCAL
+    elif xcd == "spread":
+        flags |= RP_FLAG_XCD_SPREAD
+    o = _opts(precision, init_mode, tol, rdt, r_scale, workspace_bytes, flags)
     _check(lib().rp_propagate(arr, len(cs), B.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), nB, ang, M,
                               ctypes.byref(o), _dev_ptr(out, torch.float64), None, _stream(torch)))
     return out

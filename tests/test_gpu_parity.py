@@ -197,3 +197,38 @@ def test_resident_batch_of_unequal_systems():
         for i in (0, 1):
             want = gc.oracle_phi(systems[i], B[i], philox.sample_angles(40 + i, 0, M, systems[i].N))
             assert _rel(res[i], want) < TOL[prec]
+
+
+def test_autotuner_picks_valid_parameters_and_caches(tmp_path):
+    from paper_1612_09517_amd import autotune
+    s = SpinSystem(5, 5, [1] * 10, list(np.random.default_rng(3).normal(0, 0.6, 10)), kS=1.5, kT=0.5, T_us=2.0)
+    B = np.linspace(0.0, 4.0, 6)
+    cache = str(tmp_path / "tune.json")
+    _say("autotune")
+    best = autotune.tune(s, B, precision=32, samples=4, cache=cache)
+    assert best["rdt"] in autotune.RDT and best["xcd"] in autotune.XCD
+    assert autotune.tune(s, B, precision=32, cache=cache) == best          # served from the cache
+    ang = rp.sample(s, 5, 4)
+    a = rp.propagate(s, B[None, :], ang, 4, precision=32, tiled=True, **best).cpu().numpy()
+    b = rp.propagate(s, B[None, :], ang, 4, precision=64).cpu().numpy()
+    assert np.max(np.abs(a - b) / b) < 1e-5
+
+
+def test_graph_replay_matches_direct_launches():
+    """Captured step graphs (default) and direct launches give bit-identical yields, on the
+    default stream and on a stream of the caller's, over chunks and fields that finish early."""
+    s = SpinSystem(5, 5, [1] * 10, list(np.random.default_rng(8).normal(0, 0.6, 10)), kS=2.0, kT=0.5, T_us=1.5)
+    B = np.array([[0.0, 1.0, 3.0, 6.0]])
+    ang = rp.sample(s, 21, 6)
+    _say("graph replay")
+    for prec in (32, 64):
+        direct = rp.propagate(s, B, ang, 6, precision=prec, tiled=True, graph=False).cpu().numpy()
+        graph = rp.propagate(s, B, ang, 6, precision=prec, tiled=True).cpu().numpy()
+        assert np.array_equal(direct, graph)
+        small = rp.propagate(s, B, ang, 6, precision=prec, tiled=True, workspace_bytes=6 * 10 ** 6).cpu().numpy()
+        assert np.array_equal(direct, small)
+        side = torch.cuda.Stream()
+        with torch.cuda.stream(side):
+            again = rp.propagate(s, B, ang, 6, precision=prec, tiled=True)
+        side.synchronize()
+        assert np.array_equal(direct, again.cpu().numpy())
