@@ -12,7 +12,8 @@
  *   - Units: hyperfine couplings, exchange and fields in mT (converted with
  *     gamma to rad/us); rate constants k_S, k_T in 1/us; times in us.
  *   - Hamiltonian (Eq. 1): H = omega (S1z + S2z) + sum_k a_k I_k.S_i(k) + 2 J S1.S2
- *     with omega = gamma |B| along z (the yield is even in omega), no nuclear
+ *     with omega = gamma B along z (B < 0 reverses the field; single-wavepacket yields
+ *     then differ, the ensemble yield is even in B), no nuclear
  *     Zeeman terms, hbar = 1.  Recombination by the Haberkorn operator
  *     K = k_S/2 P_S + k_T/2 P_T (Eq. 2-4); wavepackets evolve by
  *     exp(-iHt - Kt) (Eq. 13).

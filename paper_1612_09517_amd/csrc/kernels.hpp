@@ -44,7 +44,7 @@ struct SysArgs {
 // Per-field constants of one Chebyshev step.
 template <typename R>
 struct FieldDev {
-  R omega;        // gamma |B|
+  R omega;        // gamma B
   R c_re, c_im;   // shift of the kernel operator (includes -i dk/2 when P_T is dissipative)
   R s1, s2;       // 1/r and 2/r
 };

@@ -288,7 +288,7 @@ static bool plan_field_once(const SystemSpec &s, double B_mT, double tol, double
                             double chol_tol, FieldPlan &out, std::string &msg, double &log_growth) {
   out = FieldPlan();
   out.B_mT = B_mT;
-  out.omega = s.gamma * std::fabs(B_mT);
+  out.omega = s.gamma * B_mT;   // signed: B < 0 reverses the field along z
   const double dk = std::fabs(s.kS - s.kT);
   // Spectrum of H: per-radical Lanczos extremes (with a relative safety margin), else the
   // triangle-inequality bound.

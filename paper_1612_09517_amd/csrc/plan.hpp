@@ -37,7 +37,7 @@ struct SystemSpec {
 
 struct FieldPlan {
   double B_mT = 0.0;
-  double omega = 0.0;          // gamma * |B|, rad/us
+  double omega = 0.0;          // gamma * B, rad/us
   double rho = 0.0;            // bound on the spectral radius of H
   double r = 0.0;              // Chebyshev half-width
   double c_re = 0.0, c_im = 0.0;   // expansion centre c (G' - c)/r

@@ -232,3 +232,44 @@ def test_graph_replay_matches_direct_launches():
             again = rp.propagate(s, B, ang, 6, precision=prec, tiled=True)
         side.synchronize()
         assert np.array_equal(direct, again.cpu().numpy())
+
+
+# --------------------------------------------------------------------------- edge cases
+def test_empty_inputs_are_no_ops():
+    s = workloads.tiny_c1().systems[0]
+    ang = rp.sample(s, 1, 0)
+    assert ang.shape == (0, 3, 2)
+    out = rp.propagate(s, np.zeros((1, 0)), ang, 0)
+    assert out.numel() == 0
+    out = rp.propagate(s, np.array([[1.0]]), rp.sample(s, 1, 2), 2)   # one field
+    assert out.shape == (1, 1, 2)
+
+
+def test_negative_fields_and_single_step():
+    """A negative field reverses the Zeeman term (single-wavepacket yields differ from those at
+    +B; only the ensemble yield is even in B) and matches the oracle sample by sample; a
+    horizon of one short step does too."""
+    s = SpinSystem(2, 1, [1, 2, 1], [0.7, -0.4, 0.3], J_mT=0.3, kS=1.2, kT=0.4, T_us=0.004)
+    B = np.array([[-2.0, 2.0]])
+    ang = rp.sample(s, 9, 4)
+    phi = rp.propagate(s, B, ang, 4).cpu().numpy()[0]
+    want = gc.oracle_phi(s, B[0], philox.sample_angles(9, 0, 4, 3))
+    assert _rel(phi, want) < 1e-10
+    assert rp.plan_field(s, 2.0)["n_steps"] == 1
+
+
+def test_no_recombination_gives_zero_yield():
+    s = SpinSystem(2, 1, [1, 1, 1], [0.8, 0.3, 0.5], kS=0.0, kT=0.0, T_us=2.0)
+    phi = rp.propagate(s, np.array([[0.0, 1.0]]), rp.sample(s, 2, 3), 3).cpu().numpy()
+    assert np.all(phi == 0.0)
+
+
+def test_invalid_arguments_raise():
+    s = workloads.tiny_c1().systems[0]
+    ang = rp.sample(s, 1, 2)
+    with pytest.raises(rp.RpError):
+        rp.propagate(s, np.array([[np.nan]]), ang, 2)
+    with pytest.raises(rp.RpError):
+        rp.propagate(SpinSystem(1, 0, [1], [0.5], kS=1.0, kT=1.0, T_us=0.0), np.array([[1.0]]), ang[:, :1].contiguous(), 2)
+    with pytest.raises(rp.RpError):
+        rp.propagate(s, np.array([[1.0]]), ang, 2, precision=16)
