@@ -51,7 +51,7 @@ def measured_traffic(precision, terms_per_step, elements_per_launch):
     """HBM bytes per term launch from the committed counter summary, or None when the
     kernel source has changed since the counters were taken (or for FP64, not measured)."""
     import hashlib
-    f = os.path.join(ROOT, "profiles", "k_cheb_half_c2_traffic.json")
+    f = os.path.join(ROOT, "profiles", "k_cheb_tile_c2_traffic.json")
     if precision != 32 or not os.path.exists(f):
         return None
     doc = json.load(open(f))
@@ -335,7 +335,7 @@ def main():
                      "traffic": measured_traffic(args.precision, int(nterms),
                                                  prof["elements"] / max(prof["term_launches"], 1)),
                      "algorithmic_bytes_per_launch": prof["elements"] * bpe / max(prof["term_launches"], 1),
-                     "kernel": "k_cheb (Chebyshev term)", "avg_launch_us": prof["term_ms"] * 1e3 / max(prof["term_launches"], 1),
+                     "kernel": "k_cheb_tile (Chebyshev term; three launch variants)", "avg_launch_us": prof["term_ms"] * 1e3 / max(prof["term_launches"], 1),
                      "bytes_per_element_term": bpe, "terms_per_step": nterms,
                      "term_time_frac": prof["term_ms"] / max(prof["total_ms"], 1e-9),
                      "quad_time_frac": prof["quad_ms"] / max(prof["total_ms"], 1e-9)},

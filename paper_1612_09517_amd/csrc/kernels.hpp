@@ -25,6 +25,32 @@ struct cx {
   R x, y;
 };
 
+// Loads and stores with the non-temporal hint (ON = true), for data touched once per launch,
+// so that it does not displace from the caches the data that is re-read: the partner tiles of
+// phi_n within a launch, and (when the chunk fits the Infinity Cache) phi_{n+1} for the next.
+template <typename R>
+using cxv = R __attribute__((ext_vector_type(2)));
+template <bool ON, typename R>
+__device__ __forceinline__ cx<R> ld_nt(const cx<R> *p) {
+  if constexpr (ON) {
+    const cxv<R> v = __builtin_nontemporal_load(reinterpret_cast<const cxv<R> *>(p));
+    return {v.x, v.y};
+  } else {
+    return *p;
+  }
+}
+template <bool ON, typename R>
+__device__ __forceinline__ void st_nt(cx<R> *p, cx<R> v) {
+  if constexpr (ON) {
+    cxv<R> t;
+    t.x = v.x;
+    t.y = v.y;
+    __builtin_nontemporal_store(t, reinterpret_cast<cxv<R> *>(p));
+  } else {
+    *p = v;
+  }
+}
+
 // Per-system constants in the kernel-argument segment (uniform across the grid).
 template <typename R>
 struct SysArgs {

@@ -239,7 +239,7 @@ __device__ __forceinline__ void flip_half(bool r1, int bit, R f, cx<R> p0, cx<R>
 
 // Everything after H x: diagonal, exchange, i beta P_S, shift and scale, recurrence,
 // stores of phi_{n+1}, its singlet amplitude and the accumulator.
-template <typename R, int MODE>
+template <typename R, int MODE, bool NT>
 __device__ __forceinline__ void finish_term(const TermArgs<R> &ta, const SysArgs<R> &sa, const FieldDev<R> &fp,
                                             int fi, int64_t job, int64_t M, R h1, R h2, cx<R> x0, cx<R> x1,
                                             cx<R> x2, cx<R> x3, cx<R> o0, cx<R> o1, cx<R> o2, cx<R> o3,
@@ -270,28 +270,29 @@ __device__ __forceinline__ void finish_term(const TermArgs<R> &ta, const SysArgs
   const int64_t Z = sa.Z;
   const int64_t e = job * Z * 4 + M;
   cx<R> *O = ta.phio + e;
-  O[0] = z0;
-  O[Z] = z1;
-  O[2 * Z] = z2;
-  O[3 * Z] = z3;
-  ta.dnext[job * sa.Z + M] = csub(z1, z2);
+  st_nt<NT>(O, z0);
+  st_nt<NT>(O + Z, z1);
+  st_nt<NT>(O + 2 * Z, z2);
+  st_nt<NT>(O + 3 * Z, z3);
+  st_nt<true>(ta.dnext + job * sa.Z + M, csub(z1, z2));
   const cx<R> *cf = ta.coef + (int64_t)fi * ta.n_terms;
   cx<R> *A = ta.acc + e;
   if (MODE == kFirst) {
     const cx<R> a0 = cf[0], a1 = cf[1];
-    A[0] = cadd(cmul(a0, x0), cmul(a1, z0));
-    A[Z] = cadd(cmul(a0, x1), cmul(a1, z1));
-    A[2 * Z] = cadd(cmul(a0, x2), cmul(a1, z2));
-    A[3 * Z] = cadd(cmul(a0, x3), cmul(a1, z3));
-    ta.dfirst[job * sa.Z + M] = csub(x1, x2);
+    st_nt<NT>(A, cadd(cmul(a0, x0), cmul(a1, z0)));
+    st_nt<NT>(A + Z, cadd(cmul(a0, x1), cmul(a1, z1)));
+    st_nt<NT>(A + 2 * Z, cadd(cmul(a0, x2), cmul(a1, z2)));
+    st_nt<NT>(A + 3 * Z, cadd(cmul(a0, x3), cmul(a1, z3)));
+    st_nt<true>(ta.dfirst + job * sa.Z + M, csub(x1, x2));
   } else if (MODE == kAcc3) {
     // acc += a_{n-1} phi_{n-1} + a_n phi_n + a_{n+1} phi_{n+1}
     const cx<R> am = cf[ta.n - 1], a0 = cf[ta.n], ap = cf[ta.n + 1];
-    const cx<R> v0 = A[0], v1 = A[Z], v2 = A[2 * Z], v3 = A[3 * Z];
-    A[0] = cadd(v0, cadd(cadd(cmul(am, o0), cmul(a0, x0)), cmul(ap, z0)));
-    A[Z] = cadd(v1, cadd(cadd(cmul(am, o1), cmul(a0, x1)), cmul(ap, z1)));
-    A[2 * Z] = cadd(v2, cadd(cadd(cmul(am, o2), cmul(a0, x2)), cmul(ap, z2)));
-    A[3 * Z] = cadd(v3, cadd(cadd(cmul(am, o3), cmul(a0, x3)), cmul(ap, z3)));
+    const cx<R> v0 = ld_nt<NT>(A), v1 = ld_nt<NT>(A + Z), v2 = ld_nt<NT>(A + 2 * Z),
+                v3 = ld_nt<NT>(A + 3 * Z);
+    st_nt<NT>(A, cadd(v0, cadd(cadd(cmul(am, o0), cmul(a0, x0)), cmul(ap, z0))));
+    st_nt<NT>(A + Z, cadd(v1, cadd(cadd(cmul(am, o1), cmul(a0, x1)), cmul(ap, z1))));
+    st_nt<NT>(A + 2 * Z, cadd(v2, cadd(cadd(cmul(am, o2), cmul(a0, x2)), cmul(ap, z2))));
+    st_nt<NT>(A + 3 * Z, cadd(v3, cadd(cadd(cmul(am, o3), cmul(a0, x3)), cmul(ap, z3))));
   }
 }
 
@@ -301,7 +302,7 @@ __device__ __forceinline__ void finish_term(const TermArgs<R> &ta, const SysArgs
 // the tile is staged in LDS and those partners are read from it.  Partners along the slow
 // spin-1/2 axes are read from global memory in batches of 8 loads; higher spins follow with
 // workgroup-uniform digits.
-template <typename R, int MODE>
+template <typename R, int MODE, bool NT>
 __global__ __launch_bounds__(256) void k_cheb_tile(TermArgs<R> ta, SysArgs<R> sa) {
   __shared__ cx<R> tile[kBlock * 4];
   __shared__ double lds[4];
@@ -324,10 +325,10 @@ __global__ __launch_bounds__(256) void k_cheb_tile(TermArgs<R> ta, SysArgs<R> sa
     x3 = X[3 * Z + M];
     if (MODE != kFirst) {
       const cx<R> *O = ta.phio + job * Z * 4 + M;
-      o0 = O[0];
-      o1 = O[Z];
-      o2 = O[2 * Z];
-      o3 = O[3 * Z];
+      o0 = ld_nt<NT>(O);
+      o1 = ld_nt<NT>(O + Z);
+      o2 = ld_nt<NT>(O + 2 * Z);
+      o3 = ld_nt<NT>(O + 3 * Z);
     }
   }
   tile[tid] = x0;                 // planar tile: tile[e * 256 + t]
@@ -440,7 +441,7 @@ __global__ __launch_bounds__(256) void k_cheb_tile(TermArgs<R> ta, SysArgs<R> sa
         }
       }
     }
-    finish_term<R, MODE>(ta, sa, fp, fi, job, M, h1, h2, x0, x1, x2, x3, o0, o1, o2, o3, y0, y1, y2, y3);
+    finish_term<R, MODE, NT>(ta, sa, fp, fi, job, M, h1, h2, x0, x1, x2, x3, o0, o1, o2, o3, y0, y1, y2, y3);
     if (MODE == kFirst)
       nrm = (double)x0.x * x0.x + (double)x0.y * x0.y + (double)x1.x * x1.x + (double)x1.y * x1.y +
             (double)x2.x * x2.x + (double)x2.y * x2.y + (double)x3.x * x3.x + (double)x3.y * x3.y;
@@ -452,7 +453,7 @@ __global__ __launch_bounds__(256) void k_cheb_tile(TermArgs<R> ta, SysArgs<R> sa
 }
 
 // One Chebyshev term for any mix of spins (mixed-radix digits, partners from global memory).
-template <typename R, int MODE>
+template <typename R, int MODE, bool NT>
 __global__ __launch_bounds__(256) void k_cheb_gen(TermArgs<R> ta, SysArgs<R> sa) {
   __shared__ double lds[4];
   const int64_t total = (int64_t)ta.njobs * ta.nbx;
@@ -471,10 +472,10 @@ __global__ __launch_bounds__(256) void k_cheb_gen(TermArgs<R> ta, SysArgs<R> sa)
     const cx<R> x0 = X[M], x1 = X[Z + M], x2 = X[2 * Z + M], x3 = X[3 * Z + M];
     if (MODE != kFirst) {
       const cx<R> *O = ta.phio + job * Z * 4 + M;
-      o0 = O[0];
-      o1 = O[Z];
-      o2 = O[2 * Z];
-      o3 = O[3 * Z];
+      o0 = ld_nt<NT>(O);
+      o1 = ld_nt<NT>(O + Z);
+      o2 = ld_nt<NT>(O + 2 * Z);
+      o3 = ld_nt<NT>(O + 3 * Z);
     }
     cx<R> y0 = zero, y1 = zero, y2 = zero, y3 = zero;
     R h1 = R(0), h2 = R(0);
@@ -511,7 +512,7 @@ __global__ __launch_bounds__(256) void k_cheb_gen(TermArgs<R> ta, SysArgs<R> sa)
         }
       }
     }
-    finish_term<R, MODE>(ta, sa, fp, fi, job, M, h1, h2, x0, x1, x2, x3, o0, o1, o2, o3, y0, y1, y2, y3);
+    finish_term<R, MODE, NT>(ta, sa, fp, fi, job, M, h1, h2, x0, x1, x2, x3, o0, o1, o2, o3, y0, y1, y2, y3);
     if (MODE == kFirst)
       nrm = (double)x0.x * x0.x + (double)x0.y * x0.y + (double)x1.x * x1.x + (double)x1.y * x1.y +
             (double)x2.x * x2.x + (double)x2.y * x2.y + (double)x3.x * x3.x + (double)x3.y * x3.y;
@@ -547,10 +548,10 @@ __global__ __launch_bounds__(256) void k_quad(QuadArgs<R> qa) {
       cx<R> W[RC];
 #pragma unroll
       for (int r = 0; r < RC; ++r) W[r] = {R(0), R(0)};
-      cx<R> vn = dp[0];
+      cx<R> vn = ld_nt<true>(dp);
       for (int n = 0; n < qa.n_terms; ++n) {
         const cx<R> v = vn;
-        if (n + 1 < qa.n_terms) vn = dp[(int64_t)(n + 1) * qa.slab];
+        if (n + 1 < qa.n_terms) vn = ld_nt<true>(dp + (int64_t)(n + 1) * qa.slab);
         cx<R> u;
         switch (n & 3) {          // multiply by (-i)^n
           case 0: u = v; break;
@@ -579,6 +580,27 @@ __global__ __launch_bounds__(256) void k_quad(QuadArgs<R> qa) {
   if (threadIdx.x == 0) {
     qa.part[(job * qa.nbx + bx) * 2] = s0;
     qa.part[(job * qa.nbx + bx) * 2 + 1] = s1;
+  }
+}
+
+template <typename R, int MODE, bool NT>
+static void launch_term_t(bool tiled, unsigned grid, hipStream_t st, const TermArgs<R> &ta, const SysArgs<R> &sa) {
+  if (tiled)
+    hipLaunchKernelGGL((k_cheb_tile<R, MODE, NT>), dim3(grid), dim3(kBlock), 0, st, ta, sa);
+  else
+    hipLaunchKernelGGL((k_cheb_gen<R, MODE, NT>), dim3(grid), dim3(kBlock), 0, st, ta, sa);
+}
+
+template <typename R>
+static void launch_term(int mode, bool tiled, bool nt, unsigned grid, hipStream_t st, const TermArgs<R> &ta,
+                        const SysArgs<R> &sa) {
+  switch (mode * 2 + (nt ? 1 : 0)) {
+    case kFirst * 2: launch_term_t<R, kFirst, false>(tiled, grid, st, ta, sa); break;
+    case kFirst * 2 + 1: launch_term_t<R, kFirst, true>(tiled, grid, st, ta, sa); break;
+    case kPlain * 2: launch_term_t<R, kPlain, false>(tiled, grid, st, ta, sa); break;
+    case kPlain * 2 + 1: launch_term_t<R, kPlain, true>(tiled, grid, st, ta, sa); break;
+    case kAcc3 * 2: launch_term_t<R, kAcc3, false>(tiled, grid, st, ta, sa); break;
+    default: launch_term_t<R, kAcc3, true>(tiled, grid, st, ta, sa); break;
   }
 }
 
@@ -796,14 +818,18 @@ __global__ __launch_bounds__(MAXB) void k_resident(ResArgs<R> ra) {
 }
 
 // ----------------------------------------------------------------------------- per-step finalisation
+// One workgroup per job: sums the per-workgroup partials of the quadrature and of the norm.
 __global__ __launch_bounds__(256) void k_finalize(FinArgs fa) {
-  const int64_t job = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (job >= fa.njobs) return;
+  __shared__ double lds[4];
+  const int64_t job = blockIdx.x;
   double y = 0.0, nrm = 0.0;
-  for (int64_t b = 0; b < fa.nbx; ++b) {
+  for (int64_t b = threadIdx.x; b < fa.nbx; b += kBlock) {
     y += fa.part_q[(job * fa.nbx + b) * 2];
     nrm += fa.part_norm[job * fa.nbx + b];
   }
+  y = block_sum(y, lds);
+  nrm = block_sum(nrm, lds);
+  if (threadIdx.x != 0) return;
   const int fi = fa.job_field[job];
   const int32_t step = fa.stepc[job];
   fa.stepc[job] = step + 1;
@@ -975,9 +1001,8 @@ static int read_opts(const rp_opts *o, Opts &out) {
     out.init_mode = o->init_mode;
     if (o->tol < 0 || o->rdt < 0 || o->r_scale < 0 || o->workspace_bytes < 0)
       return fail(RP_EINVAL, "negative option");
-    if ((o->flags & ~(RP_FLAG_PROFILE | RP_FLAG_TILED | RP_FLAG_XCD_LOCAL | RP_FLAG_XCD_SPREAD | RP_FLAG_NO_GRAPH)) !=
-            0 ||
-        o->reserved != 0)
+    const int known = RP_FLAG_PROFILE | RP_FLAG_TILED | RP_FLAG_XCD_LOCAL | RP_FLAG_XCD_SPREAD | RP_FLAG_NO_GRAPH;
+    if ((o->flags & ~known) != 0 || o->reserved != 0)
       return fail(RP_EINVAL, "unknown flags or nonzero reserved field");
     out.flags = o->flags;
     if (o->tol > 0) out.tol = o->tol;
@@ -1199,6 +1224,11 @@ static int propagate_system(const SystemSpec &spec, const double *B, int nB, con
   int remap = vec_bytes <= ((int64_t)1 << 20) ? 1 : 0;
   if (op.flags & RP_FLAG_XCD_LOCAL) remap = 1;
   if (op.flags & RP_FLAG_XCD_SPREAD) remap = 0;
+  // Streaming (non-temporal) loads and stores of phi_{n-1}, phi_{n+1} and the accumulator when
+  // the chunk's three wavepacket buffers exceed the 256 MB Infinity Cache: they would not
+  // survive there until the next launch anyway, and the hint leaves the L2 to the partner
+  // tiles of phi_n.  The singlet amplitudes, read only by the quadrature, always stream.
+  const bool stream_nt = 3 * chunk * vec_bytes > ((int64_t)256 << 20);
   const double rtol = op.precision == 64 ? 1e-9 : 1e-4;
   // Graph replay of the step launches (not while profiling: the events are per launch).
   const bool use_graph = !log.on && !(op.flags & RP_FLAG_NO_GRAPH);
@@ -1259,10 +1289,7 @@ static int propagate_system(const SystemSpec &spec, const double *B, int nB, con
       ta.dfirst = D;
       const double eb = (double)sizeof(R) / 4.0;   // bytes per element, in units of complex-FP32 bytes
       log.mark(st);
-      if (sa.tiled)
-        hipLaunchKernelGGL((k_cheb_tile<R, kFirst>), dim3(grid), dim3(kBlock), 0, st, ta, sa);
-      else
-        hipLaunchKernelGGL((k_cheb_gen<R, kFirst>), dim3(grid), dim3(kBlock), 0, st, ta, sa);
+      launch_term<R>(kFirst, sa.tiled != 0, stream_nt, grid, st, ta, sa);
       double bytes = 28.0 * eb;
       for (int n = 1; n + 1 < nt; ++n) {
         // phi_{n+1} = 2 Gh phi_n - phi_{n-1}, written over phi_{n-1}; every third launch also adds
@@ -1272,17 +1299,7 @@ static int propagate_system(const SystemSpec &spec, const double *B, int nB, con
         ta.n = n;
         ta.dnext = D + (int64_t)(n + 1) * slab;
         const bool acc3 = (n % 3) == 0;
-        if (sa.tiled) {
-          if (acc3)
-            hipLaunchKernelGGL((k_cheb_tile<R, kAcc3>), dim3(grid), dim3(kBlock), 0, st, ta, sa);
-          else
-            hipLaunchKernelGGL((k_cheb_tile<R, kPlain>), dim3(grid), dim3(kBlock), 0, st, ta, sa);
-        } else {
-          if (acc3)
-            hipLaunchKernelGGL((k_cheb_gen<R, kAcc3>), dim3(grid), dim3(kBlock), 0, st, ta, sa);
-          else
-            hipLaunchKernelGGL((k_cheb_gen<R, kPlain>), dim3(grid), dim3(kBlock), 0, st, ta, sa);
-        }
+        launch_term<R>(acc3 ? kAcc3 : kPlain, sa.tiled != 0, stream_nt, grid, st, ta, sa);
         bytes += (acc3 ? 42.0 : 26.0) * eb;
       }
       log.mark(st);
@@ -1326,14 +1343,22 @@ static int propagate_system(const SystemSpec &spec, const double *B, int nB, con
       fa.kS = spec.kS;
       fa.kmin = kmin;
       fa.rtol = rtol;
-      hipLaunchKernelGGL(k_finalize, dim3(grid1(active)), dim3(256), 0, st, fa);
+      hipLaunchKernelGGL(k_finalize, dim3((unsigned)active), dim3(kBlock), 0, st, fa);
     };
     // One captured graph per (active jobs, buffer parity) of this chunk, replayed every step.
-    std::map<std::pair<int64_t, int>, hipGraphExec_t> graphs;
+    using GraphKey = std::pair<int64_t, int>;
+    std::map<GraphKey, hipGraphExec_t> graphs;
+    // HIP does not promise that destroying an executable graph waits for its launches, so the
+    // chunk's launches are waited for before its graphs are destroyed.
     struct GraphsGuard {
-      std::map<std::pair<int64_t, int>, hipGraphExec_t> &g;
-      ~GraphsGuard() { for (auto &kv : g) (void)hipGraphExecDestroy(kv.second); }
-    } graphs_guard{graphs};
+      std::map<GraphKey, hipGraphExec_t> &g;
+      hipStream_t s;
+      ~GraphsGuard() {
+        if (g.empty()) return;
+        (void)hipStreamSynchronize(s);
+        for (auto &kv : g) (void)hipGraphExecDestroy(kv.second);
+      }
+    } graphs_guard{graphs, st};
     const int64_t steps_max = nsteps[job_field[j0]];
     for (int64_t t = 0; t < steps_max; ++t) {
       // Jobs of fields with more than t steps form the prefix [0, C(t)) of the sorted list.
@@ -1342,7 +1367,7 @@ static int propagate_system(const SystemSpec &spec, const double *B, int nB, con
       const int64_t active = std::min<int64_t>(nj, std::max<int64_t>(0, nf * M - j0));
       if (active <= 0) break;
       if (use_graph) {
-        const auto key = std::make_pair(active, ip);
+        const GraphKey key{active, ip};
         auto it = graphs.find(key);
         if (it == graphs.end()) {
           HIPCHK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
