@@ -302,6 +302,7 @@ __device__ __forceinline__ void finish_term(const TermArgs<R> &ta, const SysArgs
 // the tile is staged in LDS and those partners are read from it.  Partners along the slow
 // spin-1/2 axes are read from global memory in batches of 8 loads; higher spins follow with
 // workgroup-uniform digits.
+constexpr int kSlowBatch = 8;   // slow-axis partner loads issued together
 template <typename R, int MODE, bool NT>
 __global__ __launch_bounds__(256) void k_cheb_tile(TermArgs<R> ta, SysArgs<R> sa) {
   __shared__ cx<R> tile[kBlock * 4];
@@ -361,10 +362,10 @@ __global__ __launch_bounds__(256) void k_cheb_tile(TermArgs<R> ta, SysArgs<R> sa
         flip_half(r1, bit, sa.f[k][0], p0, p1, y0, y1, y2, y3);
       }
     }
-    for (int k0 = kf; k0 < nh; k0 += 8) {
-      cx<R> pa[8], pb[8];
+    for (int k0 = kf; k0 < nh; k0 += kSlowBatch) {
+      cx<R> pa[kSlowBatch], pb[kSlowBatch];
 #pragma unroll
-      for (int j = 0; j < 8; ++j) {
+      for (int j = 0; j < kSlowBatch; ++j) {
         const int k = k0 + j;
         if (k < nh) {
           const int bit = (int)((M >> k) & 1);
@@ -377,7 +378,7 @@ __global__ __launch_bounds__(256) void k_cheb_tile(TermArgs<R> ta, SysArgs<R> sa
         }
       }
 #pragma unroll
-      for (int j = 0; j < 8; ++j) {
+      for (int j = 0; j < kSlowBatch; ++j) {
         const int k = k0 + j;
         if (k < nh) {
           const int bit = (int)((M >> k) & 1);

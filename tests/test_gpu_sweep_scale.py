@@ -52,3 +52,29 @@ def test_full_size_fp32_tracks_fp64():
     p32 = _run(32, B, 8)
     assert np.max(np.abs(p32 - p64) / p64) < 1e-5
     assert np.all((p64 > 0) & (p64 < 1))
+
+
+def test_streaming_hints_leave_results_unchanged():
+    """A chunk whose three wavepacket buffers exceed the 256 MB Infinity Cache is propagated with
+    non-temporal loads and stores of phi_{n-1}, phi_{n+1} and the accumulator; a smaller
+    workspace (fewer jobs per launch) takes the cached path.  Both give bit-identical yields,
+    which agree with the sparse oracle (9+9 spin-1/2, Z = 2^18, one short step)."""
+    import gpu_common as gc
+    from oracle import philox
+    a = list(np.random.default_rng(18).normal(0.0, 0.7, 18))
+    s = workloads.SpinSystem(9, 9, [1] * 18, a, 0.0, 2.0, 0.5, 0.02)
+    B = np.array([[0.5, 3.0, 6.0]])
+    M = 4
+    ang = rp.sample(s, 77, M)
+    want = gc.oracle_phi_sparse(s, [0.5], philox.sample_angles(77, 0, 1, 18))[0, 0]
+    for prec, tol in ((32, 1e-5), (64, 1e-9)):
+        cb = 8 * (prec // 32)
+        vec = 4 * s.Z * cb
+        nt = max(rp.plan_field(s, float(b), precision=prec)["n_terms"] for b in B[0])
+        per_job = 3 * vec + nt * s.Z * cb + (s.Z // 256) * 24 + 32
+        assert 3 * B.shape[1] * M * vec > 256 << 20          # default chunk streams
+        print("streaming: precision", prec, "n_terms", nt, flush=True)
+        big = rp.propagate(s, B, ang, M, precision=prec).cpu().numpy()
+        small = rp.propagate(s, B, ang, M, precision=prec, workspace_bytes=int(2.5 * per_job)).cpu().numpy()
+        assert np.array_equal(big, small)
+        assert abs(big[0, 0, 0] - want) < tol * want, (prec, big[0, 0, 0], want)
