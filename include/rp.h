@@ -76,6 +76,10 @@ typedef struct rp_opts {
   int64_t workspace_bytes;  /* cap on device workspace per call; 0 selects half of free memory */
   int32_t flags;            /* bit mask of RP_FLAG_* */
   int32_t reserved;         /* must be 0 */
+  double max_growth;        /* bound on the growth of the Chebyshev vectors over one step, worst case
+                               over the dissipative strip of the spectrum; steps are shortened until
+                               it holds (it limits the rounding error of the series).  0 selects
+                               1e10 (64) or 1e6 (32); otherwise >= 2. */
 } rp_opts;
 
 /* opts->flags: record HIP events around the Chebyshev-term launches of every step

@@ -32,7 +32,7 @@ class _System(ctypes.Structure):
 class _Opts(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("init_mode", ctypes.c_int32), ("tol", ctypes.c_double),
                 ("rdt", ctypes.c_double), ("r_scale", ctypes.c_double), ("workspace_bytes", ctypes.c_int64),
-                ("flags", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("flags", ctypes.c_int32), ("reserved", ctypes.c_int32), ("max_growth", ctypes.c_double)]
 
 
 _lib = None
@@ -103,10 +103,10 @@ class _CSystem:
         self.c.gamma = s.gamma if s.gamma else GAMMA_E
 
 
-def _opts(precision=64, init_mode=0, tol=0.0, rdt=0.0, r_scale=0.0, workspace_bytes=0, flags=0):
+def _opts(precision=64, init_mode=0, tol=0.0, rdt=0.0, r_scale=0.0, workspace_bytes=0, flags=0, max_growth=0.0):
     o = _Opts()
     o.precision, o.init_mode, o.tol, o.rdt, o.r_scale = precision, init_mode, tol, rdt, r_scale
-    o.workspace_bytes, o.flags, o.reserved = workspace_bytes, flags, 0
+    o.workspace_bytes, o.flags, o.reserved, o.max_growth = workspace_bytes, flags, 0, max_growth
     return o
 
 
@@ -136,7 +136,7 @@ def sample(system: SpinSystem, seed, M, first=0, stream_id=0, basis_mode=0, out=
 
 
 def propagate(systems, B_mT, angles, M, precision=64, init_mode=0, tol=0.0, rdt=0.0, r_scale=0.0,
-              workspace_bytes=0, out=None, profile=False, tiled=False, xcd=None, graph=True):
+              workspace_bytes=0, out=None, profile=False, tiled=False, xcd=None, graph=True, max_growth=0.0):
     """rp_propagate: single-wavepacket yields [n_sys][nB][M] (float64 CUDA tensor).
 
     ``systems`` is a SpinSystem or a list; ``B_mT`` is [n_sys][nB] (host);
@@ -160,7 +160,7 @@ def propagate(systems, B_mT, angles, M, precision=64, init_mode=0, tol=0.0, rdt=
         flags |= RP_FLAG_XCD_LOCAL
     elif xcd == "spread":
         flags |= RP_FLAG_XCD_SPREAD
-    o = _opts(precision, init_mode, tol, rdt, r_scale, workspace_bytes, flags)
+    o = _opts(precision, init_mode, tol, rdt, r_scale, workspace_bytes, flags, max_growth)
     _check(lib().rp_propagate(arr, len(cs), B.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), nB, ang, M,
                               ctypes.byref(o), _dev_ptr(out, torch.float64), None, _stream(torch)))
     return out
@@ -264,10 +264,10 @@ def bessel_j(x, nmax):
     return out
 
 
-def plan_field(system: SpinSystem, B_mT, precision=64, tol=0.0, rdt=0.0, r_scale=0.0):
+def plan_field(system: SpinSystem, B_mT, precision=64, tol=0.0, rdt=0.0, r_scale=0.0, max_growth=0.0):
     """Chebyshev step plan of one field: dict with r, c, dt, n_steps, n_terms, rank, x, coef, ell."""
     cs = _CSystem(system)
-    o = _opts(precision, 0, tol, rdt, r_scale)
+    o = _opts(precision, 0, tol, rdt, r_scale, max_growth=max_growth)
     info = np.zeros(8)
     dp = ctypes.POINTER(ctypes.c_double)
     _check(lib().rp_plan_field(ctypes.byref(cs.c), float(B_mT), ctypes.byref(o), info.ctypes.data_as(dp),

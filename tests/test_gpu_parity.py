@@ -273,3 +273,40 @@ def test_invalid_arguments_raise():
         rp.propagate(SpinSystem(1, 0, [1], [0.5], kS=1.0, kT=1.0, T_us=0.0), np.array([[1.0]]), ang[:, :1].contiguous(), 2)
     with pytest.raises(rp.RpError):
         rp.propagate(s, np.array([[1.0]]), ang, 2, precision=16)
+
+
+@pytest.mark.parametrize("growth", [1e2, 0.0, 1e30])
+def test_strong_dissipation_matches_oracle(growth):
+    """|kS - kT| comparable to or larger than the spectral half-width r: the Chebyshev vectors
+    can grow on the dissipative strip and the planner bounds the worst-case growth per step.
+    At a strict bound and at the default, coherent-state and basis-state (Eq. 14) yields match
+    the dense oracle; with no effective bound a call either still matches or reports
+    RP_ENOTCONV (never a silently wrong yield)."""
+    cases = [
+        SpinSystem(1, 0, [1], [0.5], kS=1.0, kT=300.0, T_us=0.05),
+        SpinSystem(2, 1, [1, 2, 1], [0.6, -0.3, 0.4], J_mT=0.5, kS=150.0, kT=2.0, T_us=0.08),
+        SpinSystem(2, 2, [1, 1, 1, 1], [0.9, 0.2, -0.7, 0.3], kS=20.0, kT=400.0, T_us=0.03),
+    ]
+    for i, s in enumerate(cases):
+        B = np.array([[0.0, 1.0, 6.0]])
+        ang = rp.sample(s, 40 + i, 4)
+        want = gc.oracle_phi(s, B[0], philox.sample_angles(40 + i, 0, 4, s.N))
+        for prec, tol in ((64, 1e-10), (32, 1e-5)):
+            for tiled in (False, True):
+                _say(f"dissipative case {i} precision {prec} growth {growth} tiled {tiled}")
+                try:
+                    phi = rp.propagate(s, B, ang, 4, precision=prec, max_growth=growth, tiled=tiled).cpu().numpy()[0]
+                except rp.RpError as e:
+                    assert growth == 1e30 and e.code == -4, (i, prec, tiled, e)
+                    continue
+                assert _rel(phi, want) < tol, (i, prec, tiled, _rel(phi, want))
+        dig = rp.sample(s, 0, s.Z, basis_mode=2)
+        want_b = gc.oracle_phi(s, B[0], philox.enumerate_basis_digits(0, s.Z, s.two_I), basis=True)
+        for prec, tol in ((64, 1e-10), (32, 1e-5)):
+            _say(f"dissipative case {i} basis states precision {prec} growth {growth}")
+            try:
+                phi = rp.propagate(s, B, dig, s.Z, init_mode=1, precision=prec, max_growth=growth).cpu().numpy()[0]
+            except rp.RpError as e:
+                assert growth == 1e30 and e.code == -4, (i, prec, "basis", e)
+                continue
+            assert _rel(phi, want_b) < tol, (i, prec, "basis", _rel(phi, want_b))
