@@ -1,0 +1,52 @@
+"""Writes exact single-wavepacket yields of the large spin-1 workload (radical 1: 4 I=1 +
+6 I=1/2, radical 2: 2 I=1 + 6 I=1/2; Z = 2,985,984; kS = kT = 1/us, J = 0) at its full size, for
+a few (sample, field) pairs.  With J = 0 and kS = kT the oracle's per-radical route applies
+(spaces of 10,368 and 1,152 states instead of 1.2e7).  Run from the repository root:
+
+    python tests/golden/make_large_golden.py          # T = 0.1 us -> large_golden.json
+    python tests/golden/make_large_golden.py --full   # the workload's T = 10 us -> large_full_golden.json
+"""
+import json
+import os
+import sys
+import time
+from multiprocessing import Pool
+
+ROOT = os.path.dirname(os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+sys.path.insert(0, ROOT)
+
+from oracle import philox, separable                   # noqa: E402
+from paper_1612_09517_amd import workloads             # noqa: E402
+
+FIELDS = [0.5, 5.0]
+
+
+def _one(args):
+    s, B, T, a = args
+    t0 = time.time()
+    phi = float(separable.yield_separable((s.n1, s.n2), s.two_I, s.a_mT, s.kS, B, T, a, gamma=s.gamma))
+    print(f"B={B} phi={phi!r} ({time.time() - t0:.0f} s)", flush=True)
+    return phi
+
+
+def main(full):
+    w = workloads.large_c4()
+    s = w.systems[0]
+    assert s.J_mT == 0.0 and s.kS == s.kT
+    T = s.T_us if full else 0.1
+    samples = [0] if full else [0, 1]
+    ang = philox.sample_angles(w.seed, 0, max(samples) + 1, s.N)
+    out = {"workload": w.name, "seed": w.seed, "stream": 0, "T_us": T, "fields_mT": FIELDS,
+           "samples": samples, "phi": {}, "source": "oracle.separable.yield_separable (scipy expm_multiply)"}
+    pairs = [(B, i) for B in FIELDS for i in samples]
+    with Pool(len(pairs)) as pool:
+        vals = pool.map(_one, [(s, B, T, ang[i]) for B, i in pairs])
+    for (B, i), v in zip(pairs, vals):
+        out["phi"][f"{B}:{i}"] = v
+    name = "large_full_golden.json" if full else "large_golden.json"
+    with open(os.path.join(os.path.dirname(os.path.abspath(__file__)), name), "w") as f:
+        json.dump(out, f, indent=1)
+
+
+if __name__ == "__main__":
+    main("--full" in sys.argv[1:])

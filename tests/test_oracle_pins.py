@@ -11,7 +11,7 @@ import numpy as np
 import pytest
 import scipy.linalg as sla
 
-from oracle import coherent, large, philox, spin, stats, yields
+from oracle import coherent, large, philox, separable, spin, stats, yields
 from paper_1612_09517_amd import workloads
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
@@ -271,6 +271,25 @@ def test_augmented_route_matches_dense():
             p = coherent.initial_wavepacket(d, a)
             y, _ = large.yield_augmented(sp_, B, 6.0, p)
             assert abs(y - fo.phi(p)) < 1e-11
+
+
+def test_separable_route_one_nucleus_closed_form():
+    """Per-radical route (J = 0, kS = kT): the mean over the two basis states (theta = 0, pi)
+    of one spin-1/2 nucleus is the Eq. 14 trace, which has a closed form at finite T."""
+    for B, T in ((0.0, 0.6), (1.0, 0.4)):
+        ys = [separable.yield_separable((1, 0), [1], [0.5], 1.0, B, T, [[c, 0.0]]) for c in (1.0, -1.0)]
+        assert abs(np.mean(ys) - _one_nucleus_closed(B, 0.5, 1.0, T)) < 1e-12
+
+
+def test_separable_route_matches_dense():
+    """Per-radical route against the dense Van Loan route, spin-1 included, J = 0, kS = kT."""
+    args = ((2, 1), [1, 2, 1], [0.6, -0.3, 0.4])
+    d = spin.DenseSystem(*args, J_mT=0.0, kS=1.5, kT=1.5)
+    for B in (0.0, 1.5):
+        fo = yields.FieldOracle(d, B, 0.15)
+        for a in philox.sample_angles(31, 0, 2, 3):
+            y = separable.yield_separable(args[0], args[1], args[2], 1.5, B, 0.15, a)
+            assert abs(y - fo.phi(coherent.initial_wavepacket(d, a))) < 1e-12
 
 
 # --------------------------------------------------------------------------- paper constants
