@@ -211,6 +211,62 @@ def other_workload(args):
     print(json.dumps(rec), flush=True)
 
 
+def trace_vs_mc(args):
+    """Deterministic trace (Eq. 14: all Z basis states |S, M>) against the Monte Carlo estimate
+    (Eq. 18: M = 200 coherent states) on one MI355X: wall times, their ratio (the paper quotes
+    only the count ratio Z/M), and the Monte Carlo error against the exact trace."""
+    import torch
+    from paper_1612_09517_amd import rp, workloads
+    torch.cuda.set_device(0)
+    w = workloads.batched_c3()
+    s = next(x for x in w.systems if x.N == args.trace_n)
+    B = w.fields_mT[0][:: max(1, w.fields_mT.shape[1] // 8)][None, :]
+    dig = rp.sample(s, 0, s.Z, basis_mode=2)
+    ang = rp.sample(s, w.seed, 200)
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        out = fn()
+        torch.cuda.synchronize()
+        return out, time.perf_counter() - t0
+
+    tr, t_tr = timed(lambda: rp.propagate(s, B, dig, s.Z, init_mode=1, precision=args.precision))
+    mc, t_mc = timed(lambda: rp.propagate(s, B, ang, 200, precision=args.precision))
+    trace = tr[0].mean(dim=1)
+    mean, err = rp.yield_stats(mc[0])
+    z = ((mean - trace).abs() / err).cpu().numpy()
+    print(json.dumps({"metric": "deterministic trace vs Monte Carlo wall time", "system": s.name, "Z": s.Z,
+                      "fields": int(B.shape[1]), "M": 200, "trace_s": t_tr, "mc_s": t_mc,
+                      "wall_ratio": t_tr / t_mc, "count_ratio": s.Z / 200,
+                      "max_abs_dev_over_eps": float(z.max()), "dtype": f"f{args.precision}"}), flush=True)
+
+
+def sampling_variance(args):
+    """Coherent states (Eq. 15) against random J_z eigenstates (Sec. V, last paragraph) as Monte
+    Carlo samples: per-sample standard deviation of the yield at equal cost, on the sweep system."""
+    import torch
+    from paper_1612_09517_amd import rp, workloads
+    torch.cuda.set_device(0)
+    w = workloads.sweep_c2()
+    s = w.systems[0]
+    B = np.array([[0.0, 2.5, 10.0]])
+    M = args.samples_per_step
+    coh = rp.propagate(s, B, rp.sample(s, w.seed, M), M, precision=args.precision)[0]
+    jz = rp.propagate(s, B, rp.sample(s, w.seed, M, basis_mode=1), M, init_mode=1, precision=args.precision)[0]
+    mc, ec = rp.yield_stats(coh)
+    mj, ej = rp.yield_stats(jz)
+    sc = (ec * np.sqrt(M)).cpu().numpy()
+    sj = (ej * np.sqrt(M)).cpu().numpy()
+    print(json.dumps({"metric": "per-sample yield std, coherent vs J_z eigenstates", "system": s.name,
+                      "fields_mT": B[0].tolist(), "M": M, "sigma_coherent": sc.tolist(), "sigma_jz": sj.tolist(),
+                      "variance_ratio_jz_over_coherent": (sj ** 2 / sc ** 2).tolist(),
+                      "mean_coherent": mc.cpu().numpy().tolist(), "mean_jz": mj.cpu().numpy().tolist(),
+                      "mean_diff_over_eps": (torch.abs(mc - mj) / torch.sqrt(ec ** 2 + ej ** 2)).cpu().numpy().tolist(),
+                      "dtype": f"f{args.precision}"}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -227,7 +283,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe", type=float, default=0.0,
                     help="only copy a buffer of this many GiB three times (calibrates HBM counters)")
-    ap.add_argument("--workload", default="sweep", choices=["sweep", "tiny", "batched", "large", "paper"])
+    ap.add_argument("--workload", default="sweep",
+                    choices=["sweep", "tiny", "batched", "large", "paper", "trace", "sampling"])
+    ap.add_argument("--trace-n", type=int, default=10, help="trace workload: nuclei of the batched system used")
     ap.add_argument("--stride", type=int, default=8, help="batched workload: take every stride-th system")
     ap.add_argument("--max-n", type=int, default=12, help="batched workload: only systems with at most this many nuclei")
     ap.add_argument("--cv", action="store_true",
@@ -245,6 +303,12 @@ def main():
         return
     if args.cv:
         cv_headline(args)
+        return
+    if args.workload == "trace":
+        trace_vs_mc(args)
+        return
+    if args.workload == "sampling":
+        sampling_variance(args)
         return
     if args.workload != "sweep":
         other_workload(args)
