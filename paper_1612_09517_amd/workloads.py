@@ -124,6 +124,16 @@ def paper_model(n_fields=64, M=200):
                     seed=1000)
 
 
+def max_state():
+    """The largest state of the parity checks: 12+11 spin-1/2 (Z = 2^23, 8.4e6 nuclear states),
+    a ~ U(-0.5, 0.5) mT, J = 0, kS = kT = 1.5 /us (so the oracle's per-radical route applies),
+    T = 0.15 us (two Chebyshev steps at 2 mT)."""
+    rng = np.random.default_rng(1023)
+    a = rng.uniform(-0.5, 0.5, 23)
+    s = SpinSystem(12, 11, [1] * 23, list(a), 0.0, 1.5, 1.5, 0.15, name="max_Z8388608")
+    return Workload("max_Z8388608", [s], np.array([[2.0]]), M=1, seed=1023)
+
+
 def one_nucleus(a_mT=0.5, k=1.0, T=10.0):
     """One spin-1/2 nucleus on radical 1 and none on radical 2 (closed-form case)."""
     return SpinSystem(1, 0, [1], [a_mT], 0.0, k, k, T, name="one_nucleus")

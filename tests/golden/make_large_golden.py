@@ -5,6 +5,7 @@ a few (sample, field) pairs.  With J = 0 and kS = kT the oracle's per-radical ro
 
     python tests/golden/make_large_golden.py          # T = 0.1 us -> large_golden.json
     python tests/golden/make_large_golden.py --full   # the workload's T = 10 us -> large_full_golden.json
+    python tests/golden/make_large_golden.py --max    # the Z = 2^23 spin-1/2 state -> max_golden.json
 """
 import json
 import os
@@ -48,5 +49,21 @@ def main(full):
         json.dump(out, f, indent=1)
 
 
+def main_max():
+    w = workloads.max_state()
+    s = w.systems[0]
+    assert s.J_mT == 0.0 and s.kS == s.kT
+    ang = philox.sample_angles(w.seed, 0, 1, s.N)
+    B = float(w.fields_mT[0, 0])
+    out = {"workload": w.name, "seed": w.seed, "stream": 0, "T_us": s.T_us, "fields_mT": [B],
+           "samples": [0], "phi": {f"{B}:0": _one((s, B, s.T_us, ang[0]))},
+           "source": "oracle.separable.yield_separable (scipy expm_multiply)"}
+    with open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "max_golden.json"), "w") as f:
+        json.dump(out, f, indent=1)
+
+
 if __name__ == "__main__":
-    main("--full" in sys.argv[1:])
+    if "--max" in sys.argv[1:]:
+        main_max()
+    else:
+        main("--full" in sys.argv[1:])

@@ -78,3 +78,54 @@ def test_streaming_hints_leave_results_unchanged():
         small = rp.propagate(s, B, ang, M, precision=prec, workspace_bytes=int(2.5 * per_job)).cpu().numpy()
         assert np.array_equal(big, small)
         assert abs(big[0, 0, 0] - want) < tol * want, (prec, big[0, 0, 0], want)
+
+
+@pytest.mark.parametrize("name", ["paper", "large"])
+def test_full_size_short_horizon_against_oracle_golden(name):
+    """The two largest states at their full size (the Sec. IV model, Z = 2^20, and the spin-1
+    workload, Z = 2,985,984) on a horizon shortened to a few Chebyshev steps, against yields
+    the oracle computed one by one (tests/golden/make_paper_golden.py, make_large_golden.py)."""
+    import dataclasses
+    g = json.load(open(os.path.join(os.path.dirname(__file__), "golden", f"{name}_golden.json")))
+    w = workloads.paper_model() if name == "paper" else workloads.large_c4()
+    s = dataclasses.replace(w.systems[0], T_us=g["T_us"])
+    B = np.asarray(g["fields_mT"])[None, :]
+    M = max(g["samples"]) + 1
+    ang = rp.sample(s, w.seed, M)
+    for prec, tol in ((64, 1e-9), (32, 1e-5)):
+        print(f"{name} full size: precision {prec} fields {list(B[0])} samples {M}", flush=True)
+        phi = rp.propagate(s, B, ang, M, precision=prec).cpu().numpy()[0]
+        for b, Bv in enumerate(g["fields_mT"]):
+            for i in g["samples"]:
+                want = g["phi"][f"{Bv}:{i}"]
+                assert abs(phi[b, i] - want) < tol * want, (name, prec, Bv, i, phi[b, i], want)
+
+
+def test_maximum_state_against_oracle_golden():
+    """The largest state of the checks, Z = 2^23 (12+11 spin-1/2; 256 MB per complex-FP32
+    wavepacket, 32,768 workgroups per launch), against the oracle's per-radical route
+    (tests/golden/make_large_golden.py --max)."""
+    g = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "max_golden.json")))
+    w = workloads.max_state()
+    s = w.systems[0]
+    assert s.T_us == g["T_us"]
+    ang = rp.sample(s, w.seed, 1)
+    want = g["phi"][f"{g['fields_mT'][0]}:0"]
+    for prec, tol in ((64, 1e-9), (32, 1e-5)):
+        print("maximum state: precision", prec, flush=True)
+        phi = rp.propagate(s, w.fields_mT, ang, 1, precision=prec).cpu().numpy()[0, 0, 0]
+        assert abs(phi - want) < tol * want, (prec, phi, want)
+
+
+def test_zero_couplings_large_mixed_radix_closed_form():
+    """Degenerate case at a large size: with every a_k = 0 the singlet is an eigenstate of
+    omega (S1z + S2z) + 2J S1.S2 and of P_S, so phi_S = 1 - exp(-kS T) for every sample,
+    whatever the nuclei (8 spin-1/2 + 10 spin-1 nuclei, Z = 15,116,544; partners along all 18
+    axes are read with zero coefficients)."""
+    s = workloads.SpinSystem(9, 9, [1] * 8 + [2] * 10, [0.0] * 18, 0.6, 2.5, 0.4, 0.3)
+    ang = rp.sample(s, 3, 1)
+    want = 1.0 - np.exp(-2.5 * 0.3)
+    for prec, tol in ((64, 1e-12), (32, 1e-6)):
+        print("zero couplings: precision", prec, flush=True)
+        phi = rp.propagate(s, np.array([[0.7, 3.0]]), ang, 1, precision=prec).cpu().numpy()[0]
+        assert np.max(np.abs(phi - want)) < tol, (prec, phi, want)
