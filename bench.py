@@ -47,16 +47,29 @@ def cpu_baseline(w, seconds_target=20.0):
                       f"({dt:.1f} s), scaled linearly to the full horizon; host has {os.cpu_count()} cores"}
 
 
+def term_kernel_digest():
+    """SHA-256 of the source that decides the term kernel's memory traffic: the device
+    structures (kernels.hpp), the Chebyshev-term kernels of rp.hip and the host function that
+    sizes chunks and launches them (propagate_system)."""
+    import hashlib
+    csrc = os.path.join(ROOT, "paper_1612_09517_amd", "csrc")
+    hip = open(os.path.join(csrc, "rp.hip")).read()
+    a = hip.index("// " + "-" * 77 + " Chebyshev term")
+    b = hip.index("// " + "-" * 77 + " in-step quadrature")
+    c = hip.index("static int propagate_system(")
+    d = hip.index("\n}\n", c) + 3
+    text = open(os.path.join(csrc, "kernels.hpp")).read() + hip[a:b] + hip[c:d]
+    return hashlib.sha256(text.encode()).hexdigest()
+
+
 def measured_traffic(precision, terms_per_step, elements_per_launch):
     """HBM bytes per term launch from the committed counter summary, or None when the
-    kernel source has changed since the counters were taken (or for FP64, not measured)."""
-    import hashlib
+    term kernel's source has changed since the counters were taken (or for FP64, not measured)."""
     f = os.path.join(ROOT, "profiles", "k_cheb_tile_c2_traffic.json")
     if precision != 32 or not os.path.exists(f):
         return None
     doc = json.load(open(f))
-    src = os.path.join(ROOT, "paper_1612_09517_amd", "csrc", "rp.hip")
-    if hashlib.sha256(open(src, "rb").read()).hexdigest() != doc["rp_hip_sha256"]:
+    if term_kernel_digest() != doc.get("term_kernel_sha256"):
         return None
     t = doc["per_launch_type"]
     n_acc3 = (terms_per_step - 2) // 3
