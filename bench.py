@@ -280,6 +280,45 @@ def sampling_variance(args):
                       "dtype": f"f{args.precision}"}), flush=True)
 
 
+def arnoldi_ablation(args):
+    """The paper's short-iterative Arnoldi propagator (RP_FLAG_ARNOLDI, Krylov dimension 16)
+    against the Chebyshev series on the sweep system (horizon cut to 2 us), and on the Sec. IV
+    model (strong dissipation, horizon 0.1 us): wall time, operator applications per
+    wavepacket and the largest relative difference of the yields, at equal seeded inputs."""
+    import dataclasses
+    import torch
+    from paper_1612_09517_amd import rp, workloads
+    torch.cuda.set_device(0)
+    for w, T, B in ((workloads.sweep_c2(), 2.0, [0.0, 5.0, 10.0]), (workloads.paper_model(), 0.1, [0.5, 3.5])):
+        s = dataclasses.replace(w.systems[0], T_us=T)
+        Bf = np.array([B])
+        M = args.samples_per_step
+        ang = rp.sample(s, w.seed, M)
+        res = {}
+        for name, kw in (("chebyshev", {}), ("arnoldi", {"arnoldi": True})):
+            rp.propagate(s, Bf[:, :1], ang[:1].contiguous(), 1, precision=args.precision, **kw)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            phi = rp.propagate(s, Bf, ang, M, precision=args.precision, **kw)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            res[name] = (phi[0].cpu().numpy(), dt)
+        rp.propagate(s, Bf, ang, M, precision=args.precision, arnoldi=True, profile=True)
+        p = rp.profile_last()
+        jobs = Bf.shape[1] * M
+        cheb_terms = sum(rp.plan_field(s, b, precision=args.precision)["n_terms"] *
+                         rp.plan_field(s, b, precision=args.precision)["n_steps"] for b in B) * M / jobs
+        diff = np.abs(res["arnoldi"][0] - res["chebyshev"][0]) / np.abs(res["chebyshev"][0])
+        print(json.dumps({"metric": "Arnoldi vs Chebyshev propagator", "system": s.name, "T_us": T, "fields_mT": B,
+                          "samples": M, "dtype": f"f{args.precision}",
+                          "chebyshev_s": res["chebyshev"][1], "arnoldi_s": res["arnoldi"][1],
+                          "time_ratio": res["arnoldi"][1] / res["chebyshev"][1],
+                          "chebyshev_terms_per_job": cheb_terms,
+                          "arnoldi_applications_per_job": p["terms_per_step"] / jobs,
+                          "arnoldi_steps_per_job": p["quad_launches"] / jobs,
+                          "max_rel_diff": float(diff.max())}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -297,7 +336,7 @@ def main():
     ap.add_argument("--copy-probe", type=float, default=0.0,
                     help="only copy a buffer of this many GiB three times (calibrates HBM counters)")
     ap.add_argument("--workload", default="sweep",
-                    choices=["sweep", "tiny", "batched", "large", "paper", "trace", "sampling"])
+                    choices=["sweep", "tiny", "batched", "large", "paper", "trace", "sampling", "arnoldi"])
     ap.add_argument("--trace-n", type=int, default=10, help="trace workload: nuclei of the batched system used")
     ap.add_argument("--stride", type=int, default=8, help="batched workload: take every stride-th system")
     ap.add_argument("--max-n", type=int, default=12, help="batched workload: only systems with at most this many nuclei")
@@ -322,6 +361,9 @@ def main():
         return
     if args.workload == "sampling":
         sampling_variance(args)
+        return
+    if args.workload == "arnoldi":
+        arnoldi_ablation(args)
         return
     if args.workload != "sweep":
         other_workload(args)

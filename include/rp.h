@@ -75,7 +75,8 @@ typedef struct rp_opts {
                                under-estimate the spectrum and exist to test RP_ENOTCONV. */
   int64_t workspace_bytes;  /* cap on device workspace per call; 0 selects half of free memory */
   int32_t flags;            /* bit mask of RP_FLAG_* */
-  int32_t reserved;         /* must be 0 */
+  int32_t krylov_dim;       /* Krylov dimension m of the short-iterative Arnoldi propagator
+                               (RP_FLAG_ARNOLDI); 0 selects 16, otherwise 2..32 */
   double max_growth;        /* bound on the growth of the Chebyshev vectors over one step, worst case
                                over the dissipative strip of the spectrum; steps are shortened until
                                it holds (it limits the rounding error of the series).  0 selects
@@ -99,6 +100,14 @@ typedef struct rp_opts {
    per step (graphs are captured per number of active wavepackets and buffer parity, on a
    stream of the library's own when the caller passes the legacy default stream). */
 #define RP_FLAG_NO_GRAPH 16
+/* opts->flags: propagate with the short-iterative Arnoldi method the paper names (Sec. III)
+   instead of the Chebyshev series: per step an m-dimensional Krylov space of A = H + i beta P_S
+   (Eq. 1-4 without the scalar decay k_T/2), the step length from the Arnoldi error estimate
+   (local error <= opts->tol, default 1e-13 for 64 and 1e-8 for 32), the in-step yield from
+   the projected singlet Gram matrix by Van Loan's block exponential.  Same outputs and units;
+   for comparison with the default propagator (every job of a call does the same launches,
+   each with its own step length; the small Krylov algebra runs on the host in FP64). */
+#define RP_FLAG_ARNOLDI 32
 
 /*
  * rp_sample -- directions of the nuclear coherent states (Eq. 18: uniform on
@@ -210,6 +219,8 @@ int rp_mlp_train_step(int32_t n_in, int32_t width, int32_t depth, float *params,
  *       writes phi_1, the accumulator and two amplitudes (28).  Doubled for FP64.
  *   [4] milliseconds in the in-step quadrature kernels, [5] their launches
  *   [6] milliseconds of the whole call, [7] Chebyshev terms per step (padded maximum)
+ * With RP_FLAG_ARNOLDI only [5] (Arnoldi steps, summed over jobs) and [7] (applications of
+ * H + i beta P_S, summed over jobs) are filled; the others are 0.
  * Returns the number of values written.
  */
 int rp_profile_last(double *out, int32_t n);

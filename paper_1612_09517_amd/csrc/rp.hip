@@ -14,6 +14,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <complex>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -178,6 +179,7 @@ struct InitArgs {
   int32_t njobs, N;
   int32_t stride[RP_MAX_NUCLEI];
   int32_t d[RP_MAX_NUCLEI];
+  int64_t vstride;              // elements between jobs; 0 selects 4Z
 };
 
 // psi_0 = |S> (x) prod_k |Omega_k>, |S> = (|ab> - |ba>)/sqrt 2 (Eq. 10, 18-19).
@@ -195,7 +197,7 @@ __global__ __launch_bounds__(256) void k_init(InitArgs<R> a) {
     const cx<double> c = t[k * (RP_MAX_TWO_I + 1) + n];
     p = {p.x * c.x - p.y * c.y, p.x * c.y + p.y * c.x};
   }
-  cx<R> *o = a.psi + job * a.Z * 4 + M;   // planes (aa, ab, ba, bb), each Z long
+  cx<R> *o = a.psi + job * (a.vstride ? a.vstride : a.Z * 4) + M;   // planes (aa, ab, ba, bb), each Z long
   o[0] = {R(0), R(0)};
   o[a.Z] = {R(p.x), R(p.y)};
   o[2 * a.Z] = {R(-p.x), R(-p.y)};
@@ -987,8 +989,9 @@ struct EventLog {
 static double gamma_of(const rp_system *s) { return s->gamma > 0.0 ? s->gamma : 176.085963023; }
 
 struct Opts {
-  int precision = 64, init_mode = 0, flags = 0;
+  int precision = 64, init_mode = 0, flags = 0, krylov = 16;
   double tol = 0, rdt = 80.0, r_scale = 1.0, chol_tol = 0, max_growth = 0;
+  bool tol_set = false;
   int64_t workspace = 0;
 };
 
@@ -1003,10 +1006,14 @@ static int read_opts(const rp_opts *o, Opts &out) {
     if (o->tol < 0 || o->rdt < 0 || o->r_scale < 0 || o->workspace_bytes < 0 || o->max_growth < 0)
       return fail(RP_EINVAL, "negative option");
     if (o->max_growth != 0 && !(o->max_growth >= 2.0)) return fail(RP_EINVAL, "max_growth must be >= 2");
-    const int known = RP_FLAG_PROFILE | RP_FLAG_TILED | RP_FLAG_XCD_LOCAL | RP_FLAG_XCD_SPREAD | RP_FLAG_NO_GRAPH;
-    if ((o->flags & ~known) != 0 || o->reserved != 0)
-      return fail(RP_EINVAL, "unknown flags or nonzero reserved field");
+    const int known =
+        RP_FLAG_PROFILE | RP_FLAG_TILED | RP_FLAG_XCD_LOCAL | RP_FLAG_XCD_SPREAD | RP_FLAG_NO_GRAPH | RP_FLAG_ARNOLDI;
+    if ((o->flags & ~known) != 0) return fail(RP_EINVAL, "unknown flags");
+    if (o->krylov_dim != 0 && (o->krylov_dim < 2 || o->krylov_dim > 32))
+      return fail(RP_EINVAL, "krylov_dim must be 0 or in [2, 32]");
+    if (o->krylov_dim) out.krylov = o->krylov_dim;
     out.flags = o->flags;
+    out.tol_set = o->tol > 0;
     if (o->tol > 0) out.tol = o->tol;
     if (o->rdt > 0) out.rdt = o->rdt;
     if (o->r_scale > 0) out.r_scale = o->r_scale;
@@ -1674,6 +1681,505 @@ extern "C" int rp_sample(const rp_system *s, uint64_t seed, uint32_t stream_id, 
   return RP_OK;
 }
 
+// ----------------------------------------------------------------------------- short-iterative Arnoldi
+// The paper's propagator (Sec. III): each step builds an m-dimensional Krylov space of the
+// wavepacket under A = H + i beta P_S (the generator without its scalar decay k_T/2, Eq. 1-4),
+// projects, and advances by exp(-i H_m dt) with dt chosen from the Arnoldi error estimate.
+// It is kept as an alternative to the Chebyshev series for comparison.  Krylov vectors of a
+// chunk: [jobs][m + 1][4Z]; every job of a chunk does the same launches, each with its own dt.
+constexpr int kSiaMax = 32;   // largest Krylov dimension
+
+// Y = A X for every job (generic mixed-radix form, partners from global memory).
+template <typename R>
+__global__ __launch_bounds__(256) void k_sia_apply(SysArgs<R> sa, const cx<R> *X, cx<R> *Y, int64_t vstride,
+                                                   int64_t nbx, int32_t njobs, const double *omega) {
+  const int64_t total = (int64_t)njobs * nbx;
+  const int64_t L = xcd_remap(blockIdx.x, total);
+  const int64_t job = L / nbx, bx = L - job * nbx;
+  const int64_t M = bx * kBlock + threadIdx.x;
+  if (M >= sa.Z) return;
+  const int64_t Z = sa.Z;
+  const cx<R> *x = X + job * vstride;
+  const cx<R> zero = {R(0), R(0)};
+  const cx<R> x0 = x[M], x1 = x[Z + M], x2 = x[2 * Z + M], x3 = x[3 * Z + M];
+  cx<R> y0 = zero, y1 = zero, y2 = zero, y3 = zero;
+  R h1 = R(0), h2 = R(0);
+  int64_t rem = M;
+  for (int k = 0; k < sa.N; ++k) {
+    const int64_t st = sa.stride[k];
+    const int dk = sa.d[k];
+    const int64_t q = rem / dk;
+    const int n = (int)(rem - q * dk);
+    rem = q;
+    const R mk = R(0.5) * R(dk - 1) - R(n);
+    const bool r1 = sa.rad[k] == 0;
+    if (r1) h1 += sa.a[k] * mk; else h2 += sa.a[k] * mk;
+    if (n > 0) {        // partner digit n-1: beta component -> alpha component
+      const R fk = sa.f[k][n - 1];
+      const cx<R> *p = x + (M - st);
+      if (r1) {
+        y0 = cadd(y0, cscale(fk, p[2 * Z]));
+        y1 = cadd(y1, cscale(fk, p[3 * Z]));
+      } else {
+        y0 = cadd(y0, cscale(fk, p[Z]));
+        y2 = cadd(y2, cscale(fk, p[3 * Z]));
+      }
+    }
+    if (n < dk - 1) {   // partner digit n+1: alpha component -> beta component
+      const R fk = sa.f[k][n];
+      const cx<R> *p = x + (M + st);
+      if (r1) {
+        y2 = cadd(y2, cscale(fk, p[0]));
+        y3 = cadd(y3, cscale(fk, p[Z]));
+      } else {
+        y1 = cadd(y1, cscale(fk, p[0]));
+        y3 = cadd(y3, cscale(fk, p[2 * Z]));
+      }
+    }
+  }
+  const R om = (R)omega[job];
+  const R hs = R(0.5) * (h1 + h2), hd = R(0.5) * (h1 - h2), hj = R(0.5) * sa.J;
+  y0 = cadd(y0, cscale(om + hs + hj, x0));
+  y1 = cadd(y1, cadd(cscale(hd - hj, x1), cscale(sa.J, x2)));
+  y2 = cadd(y2, cadd(cscale(-hd - hj, x2), cscale(sa.J, x1)));
+  y3 = cadd(y3, cscale(-om - hs + hj, x3));
+  const cx<R> t = {R(0.5) * (x1.x - x2.x), R(0.5) * (x1.y - x2.y)};
+  const cx<R> ibt = {-sa.beta * t.y, sa.beta * t.x};
+  y1 = cadd(y1, ibt);
+  y2 = csub(y2, ibt);
+  cx<R> *y = Y + job * vstride;
+  y[M] = y0;
+  y[Z + M] = y1;
+  y[2 * Z + M] = y2;
+  y[3 * Z + M] = y3;
+}
+
+// part[job][bx][i] = sum over the workgroup's indices and the four planes of conj(V_{i0+i}) V_w,
+// for i < nd; FP64 accumulation.
+template <typename R>
+__global__ __launch_bounds__(256) void k_sia_dot(const cx<R> *V, int64_t vstride, int64_t Z, int64_t nbx,
+                                                 int32_t njobs, int32_t w, int32_t i0, int32_t nd,
+                                                 cx<double> *part) {
+  __shared__ double lds[4];
+  const int64_t job = blockIdx.x / nbx, bx = blockIdx.x - job * nbx;
+  const int64_t M = bx * kBlock + threadIdx.x;
+  const bool live = M < Z;
+  const cx<R> *v = V + job * vstride;
+  cx<R> wv[4];
+  for (int e = 0; e < 4; ++e) wv[e] = live ? v[(int64_t)w * 4 * Z + e * Z + M] : cx<R>{R(0), R(0)};
+  for (int i = 0; i < nd; ++i) {
+    double re = 0.0, im = 0.0;
+    if (live)
+      for (int e = 0; e < 4; ++e) {
+        const cx<R> a = v[(int64_t)(i0 + i) * 4 * Z + e * Z + M];
+        re += (double)a.x * wv[e].x + (double)a.y * wv[e].y;
+        im += (double)a.x * wv[e].y - (double)a.y * wv[e].x;
+      }
+    re = block_sum(re, lds);
+    im = block_sum(im, lds);
+    if (threadIdx.x == 0) part[(job * nbx + bx) * kSiaMax + i] = {re, im};
+  }
+}
+
+// out[job * ostride + i] = sum over q < nq of part[job][q][i], i < ni.
+__global__ __launch_bounds__(256) void k_sia_reduce(const cx<double> *part, int64_t nq, int32_t pstride,
+                                                    int32_t ni, cx<double> *out, int64_t ostride) {
+  __shared__ double lds[4];
+  const int64_t job = blockIdx.x;
+  for (int i = 0; i < ni; ++i) {
+    double re = 0.0, im = 0.0;
+    for (int64_t q = threadIdx.x; q < nq; q += kBlock) {
+      const cx<double> p = part[(job * nq + q) * pstride + i];
+      re += p.x;
+      im += p.y;
+    }
+    re = block_sum(re, lds);
+    im = block_sum(im, lds);
+    if (threadIdx.x == 0) out[job * ostride + i] = {re, im};
+  }
+}
+
+// V_w -= sum_{i < nd} h[job][i] V_i  (one Gram-Schmidt pass).
+template <typename R>
+__global__ __launch_bounds__(256) void k_sia_axpy(cx<R> *V, int64_t vstride, int64_t Z, int64_t nbx, int32_t w,
+                                                  int32_t nd, const cx<double> *h, int64_t hstride) {
+  const int64_t job = blockIdx.x / nbx, bx = blockIdx.x - job * nbx;
+  const int64_t M = bx * kBlock + threadIdx.x;
+  if (M >= Z) return;
+  cx<R> *v = V + job * vstride;
+  for (int e = 0; e < 4; ++e) {
+    cx<R> acc = v[(int64_t)w * 4 * Z + e * Z + M];
+    for (int i = 0; i < nd; ++i) {
+      const cx<double> c = h[job * hstride + i];
+      const cx<R> a = v[(int64_t)i * 4 * Z + e * Z + M];
+      acc = csub(acc, cmul(cx<R>{(R)c.x, (R)c.y}, a));
+    }
+    v[(int64_t)w * 4 * Z + e * Z + M] = acc;
+  }
+}
+
+// Whether the residual of Arnoldi column j is rounding noise, i.e. the Krylov space became
+// invariant: its squared norm n2 against that of A v_j, sum_i |h_ij|^2 + n2 (both passes).
+__host__ __device__ inline bool sia_breakdown(const cx<double> *h1, const cx<double> *h2, int nd, double n2,
+                                              double rel2) {
+  double tot = n2;
+  for (int i = 0; i < nd; ++i) {
+    const double re = h1[i].x + h2[i].x, im = h1[i].y + h2[i].y;
+    tot += re * re + im * im;
+  }
+  return !(n2 > rel2 * tot) || !(n2 > 1e-300);
+}
+
+// V_w /= sqrt(Re nrm[job]), or V_w = 0 when the Krylov space became invariant.  h points at
+// the first Gram-Schmidt pass of the column (the second follows at +hgap).
+template <typename R>
+__global__ __launch_bounds__(256) void k_sia_scale(cx<R> *V, int64_t vstride, int64_t Z, int64_t nbx, int32_t w,
+                                                   const cx<double> *nrm, int64_t nstride, const cx<double> *h,
+                                                   int32_t hgap, double rel2) {
+  const int64_t job = blockIdx.x / nbx, bx = blockIdx.x - job * nbx;
+  const int64_t M = bx * kBlock + threadIdx.x;
+  if (M >= Z) return;
+  const double n2 = nrm[job * nstride].x;
+  const cx<double> *hj = h + job * nstride;
+  const R s = sia_breakdown(hj, hj + hgap, w, n2, rel2) ? R(0) : (R)(1.0 / sqrt(n2));
+  cx<R> *v = V + job * vstride + (int64_t)w * 4 * Z;
+  for (int e = 0; e < 4; ++e) v[e * Z + M] = cscale(s, v[e * Z + M]);
+}
+
+// Partial Gram matrix of singlet amplitudes d_a = V_a(ab) - V_a(ba), pairs a <= b < m, one
+// entry per wave: part[job][4 bx + wave][pair] = sum conj(d_a) d_b.
+template <typename R>
+__global__ __launch_bounds__(256) void k_sia_gram(const cx<R> *V, int64_t vstride, int64_t Z, int64_t nbx,
+                                                  int32_t m, cx<double> *part, int32_t pstride) {
+  const int64_t job = blockIdx.x / nbx, bx = blockIdx.x - job * nbx;
+  const int64_t M = bx * kBlock + threadIdx.x;
+  const bool live = M < Z;
+  const cx<R> *v = V + job * vstride;
+  cx<double> d[kSiaMax];
+  for (int a = 0; a < m; ++a) {
+    if (live) {
+      const cx<R> p = v[(int64_t)a * 4 * Z + Z + M], q = v[(int64_t)a * 4 * Z + 2 * Z + M];
+      d[a] = {(double)p.x - (double)q.x, (double)p.y - (double)q.y};
+    } else {
+      d[a] = {0.0, 0.0};
+    }
+  }
+  const int wave = threadIdx.x >> 6;
+  cx<double> *out = part + ((job * nbx + bx) * 4 + wave) * (int64_t)pstride;
+  int pr = 0;
+  for (int a = 0; a < m; ++a)
+    for (int b = a; b < m; ++b, ++pr) {
+      const double re = warp_sum(d[a].x * d[b].x + d[a].y * d[b].y);
+      const double im = warp_sum(d[a].x * d[b].y - d[a].y * d[b].x);
+      if ((threadIdx.x & 63) == 0) out[pr] = {re, im};
+    }
+}
+
+// V_m = sum_{a < m} g[job][a] V_a, then V_0 = V_m (the normalised state for the next step).
+template <typename R>
+__global__ __launch_bounds__(256) void k_sia_combine(cx<R> *V, int64_t vstride, int64_t Z, int64_t nbx, int32_t m,
+                                                     const cx<double> *g) {
+  const int64_t job = blockIdx.x / nbx, bx = blockIdx.x - job * nbx;
+  const int64_t M = bx * kBlock + threadIdx.x;
+  if (M >= Z) return;
+  cx<R> *v = V + job * vstride;
+  for (int e = 0; e < 4; ++e) {
+    cx<R> acc = {R(0), R(0)};
+    for (int a = 0; a < m; ++a) {
+      const cx<double> c = g[job * kSiaMax + a];
+      acc = cadd(acc, cmul(cx<R>{(R)c.x, (R)c.y}, v[(int64_t)a * 4 * Z + e * Z + M]));
+    }
+    v[(int64_t)m * 4 * Z + e * Z + M] = acc;
+  }
+  for (int e = 0; e < 4; ++e) v[e * Z + M] = v[(int64_t)m * 4 * Z + e * Z + M];
+}
+
+// Small dense complex matrices (row-major n x n) for the Krylov-space algebra on the host.
+using cplx = std::complex<double>;
+
+static void small_matmul(const std::vector<cplx> &A, const std::vector<cplx> &B, std::vector<cplx> &C, int n) {
+  C.assign((size_t)n * n, cplx(0.0, 0.0));
+  for (int i = 0; i < n; ++i)
+    for (int k = 0; k < n; ++k) {
+      const cplx a = A[(size_t)i * n + k];
+      if (a == cplx(0.0, 0.0)) continue;
+      for (int j = 0; j < n; ++j) C[(size_t)i * n + j] += a * B[(size_t)k * n + j];
+    }
+}
+
+// exp(A) by scaling and squaring with a degree-16 Taylor polynomial evaluated at A / 2^s,
+// ||A / 2^s||_1 <= 1/4 (remainder below 1e-24 relative).
+static void small_expm(const std::vector<cplx> &A, std::vector<cplx> &E, int n) {
+  double nrm = 0.0;
+  for (int j = 0; j < n; ++j) {
+    double c = 0.0;
+    for (int i = 0; i < n; ++i) c += std::abs(A[(size_t)i * n + j]);
+    nrm = std::max(nrm, c);
+  }
+  int s = 0;
+  while (nrm > 0.25 && s < 200) {
+    nrm *= 0.5;
+    ++s;
+  }
+  const double sc = std::ldexp(1.0, -s);
+  std::vector<cplx> As(A.size()), T((size_t)n * n, cplx(0.0, 0.0)), P;
+  for (size_t i = 0; i < A.size(); ++i) As[i] = A[i] * sc;
+  for (int i = 0; i < n; ++i) T[(size_t)i * n + i] = 1.0;
+  for (int k = 16; k >= 1; --k) {   // T = I + As T / k
+    small_matmul(As, T, P, n);
+    for (size_t i = 0; i < P.size(); ++i) P[i] /= (double)k;
+    for (int i = 0; i < n; ++i) P[(size_t)i * n + i] += 1.0;
+    T.swap(P);
+  }
+  for (int q = 0; q < s; ++q) {
+    small_matmul(T, T, P, n);
+    T.swap(P);
+  }
+  E.swap(T);
+}
+
+struct SiaJob {
+  double t = 0.0, beta = 1.0, phi = 0.0, dt = 0.0;
+  int64_t steps = 0;
+  bool done = false, failed = false;
+};
+constexpr int64_t kSiaMaxSteps = 1000000;   // per job; more means the step control has failed
+
+// One Arnoldi step of one job on the host: step length from the error estimate, the in-step
+// yield by Van Loan's block exponential, and the coefficients of the next normalised state.
+static void sia_host_step(const cplx *blk, int m, double T, double kS, double kT, double tol, double rel2,
+                          SiaJob &jb, cplx *g) {
+  for (int a = 0; a < kSiaMax; ++a) g[a] = 0.0;
+  if (jb.done) {
+    g[0] = 1.0;
+    return;
+  }
+  // Hessenberg matrix: H[i][j] = both Gram-Schmidt passes; H[j+1][j] = norm of the residual.
+  std::vector<cplx> X((size_t)m * m, cplx(0.0, 0.0));
+  const cplx *nrm = blk + 2 * m * (m + 1);
+  double hlast = 0.0;
+  for (int j = 0; j < m; ++j) {
+    const cplx *h1 = blk + (j * 2) * (m + 1), *h2 = blk + (j * 2 + 1) * (m + 1);
+    for (int i = 0; i <= j; ++i) X[(size_t)i * m + j] = cplx(0.0, -1.0) * (h1[i] + h2[i]);
+    // the same breakdown decision as the device's normalisation
+    const bool bd = sia_breakdown(reinterpret_cast<const cx<double> *>(h1), reinterpret_cast<const cx<double> *>(h2),
+                                  j + 1, nrm[j].real(), rel2);
+    const double hn = bd ? 0.0 : std::sqrt(nrm[j].real());
+    if (j + 1 < m) X[(size_t)(j + 1) * m + j] = cplx(0.0, -hn);
+    else hlast = hn;
+  }
+  // S[a][b] = <P_S v_a | P_S v_b> = (1/2) sum conj(d_a) d_b
+  std::vector<cplx> S((size_t)m * m);
+  const cplx *gr = nrm + m;
+  for (int a = 0, pr = 0; a < m; ++a)
+    for (int b = a; b < m; ++b, ++pr) {
+      S[(size_t)a * m + b] = 0.5 * gr[pr];
+      S[(size_t)b * m + a] = std::conj(0.5 * gr[pr]);
+    }
+  double dt = std::min(T - jb.t, jb.dt > 0.0 ? 1.5 * jb.dt : T - jb.t);
+  std::vector<cplx> E, Xs((size_t)m * m);
+  for (int tries = 0;; ++tries) {
+    for (size_t i = 0; i < X.size(); ++i) Xs[i] = X[i] * dt;
+    small_expm(Xs, E, m);
+    const double err = hlast * std::abs(E[(size_t)(m - 1) * m + 0]);
+    if (err <= tol) break;
+    if (tries >= 60 || !std::isfinite(err)) {   // no admissible step: report instead of crawling
+      jb.failed = true;
+      jb.done = true;
+      g[0] = 1.0;
+      return;
+    }
+    dt *= 0.6;
+  }
+  if (T - jb.t - dt < 1e-14 * T) dt = T - jb.t;
+  // Van Loan: exp([[-Xd^H, S], [0, Xd]] dt) = [[., G1], [0, F3]], int_0^dt e^{Xd^H s} S e^{Xd s} ds
+  // = F3^H G1, with Xd = X - (kT/2) I carrying the scalar decay of the population.
+  const int n2 = 2 * m;
+  std::vector<cplx> C((size_t)n2 * n2, cplx(0.0, 0.0)), F;
+  for (int i = 0; i < m; ++i)
+    for (int j = 0; j < m; ++j) {
+      const cplx xd = X[(size_t)i * m + j] - (i == j ? 0.5 * kT : 0.0);
+      const cplx xdh = std::conj(X[(size_t)j * m + i] - (i == j ? 0.5 * kT : 0.0));
+      C[(size_t)i * n2 + j] = -xdh * dt;
+      C[(size_t)i * n2 + m + j] = S[(size_t)i * m + j] * dt;
+      C[(size_t)(m + i) * n2 + m + j] = xd * dt;
+    }
+  small_expm(C, F, n2);
+  cplx q = 0.0;
+  for (int a = 0; a < m; ++a) q += std::conj(F[(size_t)(m + a) * n2 + m]) * F[(size_t)a * n2 + m];
+  jb.phi += kS * jb.beta * jb.beta * std::exp(-kT * jb.t) * q.real();
+  double cn = 0.0;
+  for (int a = 0; a < m; ++a) cn += std::norm(E[(size_t)a * m]);
+  cn = std::sqrt(cn);
+  for (int a = 0; a < m; ++a) g[a] = cn > 0.0 ? E[(size_t)a * m] / cn : cplx(a == 0 ? 1.0 : 0.0, 0.0);
+  jb.beta *= cn;
+  jb.t += dt;
+  jb.dt = dt;
+  if (jb.t >= T * (1.0 - 1e-14)) jb.done = true;
+  if (++jb.steps >= kSiaMaxSteps && !jb.done) {
+    jb.failed = true;
+    jb.done = true;
+  }
+}
+
+template <typename R>
+static int sia_system(const SystemSpec &spec, const double *B, int nB, const double *angles_dev, int64_t M,
+                      const Opts &op, double *phi_out, hipStream_t st) {
+  const int m = op.krylov;
+  const double tol = op.tol_set ? op.tol : (op.precision == 64 ? 1e-13 : 1e-8);
+  // A residual below 1e-14 (FP64) or 1e-6 (FP32) of |A v_j| is rounding noise: the Krylov space
+  // is invariant and the column ends the space.
+  const double rel2 = op.precision == 64 ? 1e-28 : 1e-12;
+  const int64_t Z = spec.Z;
+  const int N = spec.N();
+  const int64_t nbx = (Z + kBlock - 1) / kBlock;
+  const int64_t total_jobs = (int64_t)nB * M;
+  if (total_jobs == 0) return RP_OK;
+  const int64_t vstride = (int64_t)(m + 1) * 4 * Z;
+  const int npair = m * (m + 1) / 2;
+  const int64_t small = 2 * m * (m + 1) + m + npair;   // complex entries per job copied to the host
+  const int64_t per_job = vstride * (int64_t)sizeof(cx<R>) + nbx * kSiaMax * 16 + nbx * 4 * npair * 16 +
+                          small * 16 + kSiaMax * 16 + 64;
+  int64_t budget = op.workspace;
+  if (budget <= 0) {
+    size_t fr = 0, tot = 0;
+    HIPCHK(hipMemGetInfo(&fr, &tot));
+    budget = (int64_t)(fr / 2);
+  }
+  int64_t chunk = std::min<int64_t>({total_jobs, budget / per_job, (int64_t)256, (((int64_t)1) << 24) / nbx});
+  if (chunk < 1) return fail(RP_ENOMEM, "workspace too small for one wavepacket");
+  struct Buf {
+    void *p = nullptr;
+    ~Buf() { if (p) (void)hipFree(p); }
+  };
+  Buf bV, bPd, bPg, bSm, bG, bOm, bTab, bJs;
+  auto alloc = [&](Buf &b, size_t bytes) -> int {
+    if (hipMalloc(&b.p, std::max<size_t>(bytes, 16)) != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(RP_ENOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes failed");
+    }
+    return RP_OK;
+  };
+  int rc;
+  if ((rc = alloc(bV, (size_t)chunk * vstride * sizeof(cx<R>)))) return rc;
+  if ((rc = alloc(bPd, (size_t)chunk * nbx * kSiaMax * 16))) return rc;
+  if ((rc = alloc(bPg, (size_t)chunk * nbx * 4 * npair * 16))) return rc;
+  if ((rc = alloc(bSm, (size_t)chunk * small * 16))) return rc;
+  if ((rc = alloc(bG, (size_t)chunk * kSiaMax * 16))) return rc;
+  if ((rc = alloc(bOm, (size_t)chunk * 8))) return rc;
+  if ((rc = alloc(bJs, (size_t)total_jobs * 4))) return rc;
+  if ((rc = alloc(bTab, (size_t)std::max<int64_t>(M, 1) * std::max(N, 1) * (RP_MAX_TWO_I + 1) * sizeof(cx<double>))))
+    return rc;
+  std::vector<int32_t> job_sample(total_jobs);
+  for (int64_t j = 0; j < total_jobs; ++j) job_sample[j] = (int32_t)(j % M);
+  HIPCHK(hipMemcpyAsync(bJs.p, job_sample.data(), total_jobs * 4, hipMemcpyHostToDevice, st));
+  if (N > 0) {
+    CohArgs ca;
+    std::memset(&ca, 0, sizeof(ca));
+    ca.angles = angles_dev;
+    ca.tab = (cx<double> *)bTab.p;
+    ca.M = M;
+    ca.N = N;
+    ca.mode = op.init_mode;
+    for (int k = 0; k < N; ++k) {
+      ca.two_I[k] = spec.two_I[k];
+      ca.perm[k] = spec.perm[k];
+    }
+    hipLaunchKernelGGL(k_coherent, dim3(grid1(M * N)), dim3(256), 0, st, ca);
+    HIPCHK(hipGetLastError());
+  }
+  const SysArgs<R> sa = make_sysargs<R>(spec);
+  cx<R> *V = (cx<R> *)bV.p;
+  cx<double> *Pd = (cx<double> *)bPd.p, *Pg = (cx<double> *)bPg.p, *Sm = (cx<double> *)bSm.p;
+  std::vector<cplx> hsmall((size_t)chunk * small), hg((size_t)chunk * kSiaMax);
+  const int nth = std::max(1, (int)std::thread::hardware_concurrency());
+  for (int64_t j0 = 0; j0 < total_jobs; j0 += chunk) {
+    const int64_t nj = std::min(chunk, total_jobs - j0);
+    const unsigned grid = (unsigned)(nj * nbx);
+    std::vector<double> om(nj);
+    for (int64_t j = 0; j < nj; ++j) om[j] = spec.gamma * B[(j0 + j) / M];
+    HIPCHK(hipMemcpyAsync(bOm.p, om.data(), nj * 8, hipMemcpyHostToDevice, st));
+    {
+      InitArgs<R> ia;
+      std::memset(&ia, 0, sizeof(ia));
+      ia.psi = V;
+      ia.vstride = vstride;
+      ia.tab = (const cx<double> *)bTab.p;
+      ia.job_sample = (const int32_t *)bJs.p + j0;
+      ia.Z = Z;
+      ia.nbx = nbx;
+      ia.njobs = (int32_t)nj;
+      ia.N = N;
+      for (int k = 0; k < N; ++k) {
+        ia.stride[k] = sa.stride[k];
+        ia.d[k] = sa.d[k];
+      }
+      if (N == 0) {
+        ia.stride[0] = 1;
+        ia.d[0] = 1;
+      }
+      hipLaunchKernelGGL(k_init<R>, dim3(grid), dim3(kBlock), 0, st, ia);
+      HIPCHK(hipGetLastError());
+    }
+    std::vector<SiaJob> jobs(nj);
+    for (;;) {
+      bool all_done = true;
+      for (auto &jb : jobs) all_done = all_done && jb.done;
+      if (all_done) break;
+      for (int j = 0; j < m; ++j) {
+        const int w = j + 1;
+        hipLaunchKernelGGL(k_sia_apply<R>, dim3(grid), dim3(kBlock), 0, st, sa, V + (int64_t)j * 4 * Z,
+                           V + (int64_t)w * 4 * Z, vstride, nbx, (int32_t)nj, (const double *)bOm.p);
+        for (int pass = 0; pass < 2; ++pass) {   // classical Gram-Schmidt, twice
+          cx<double> *h = Sm + (j * 2 + pass) * (m + 1);
+          hipLaunchKernelGGL(k_sia_dot<R>, dim3(grid), dim3(kBlock), 0, st, V, vstride, Z, nbx, (int32_t)nj, w, 0,
+                             j + 1, Pd);
+          hipLaunchKernelGGL(k_sia_reduce, dim3((unsigned)nj), dim3(kBlock), 0, st, Pd, nbx, kSiaMax, j + 1, h,
+                             small);
+          hipLaunchKernelGGL(k_sia_axpy<R>, dim3(grid), dim3(kBlock), 0, st, V, vstride, Z, nbx, w, j + 1, h, small);
+        }
+        cx<double> *nr = Sm + 2 * m * (m + 1) + j;
+        hipLaunchKernelGGL(k_sia_dot<R>, dim3(grid), dim3(kBlock), 0, st, V, vstride, Z, nbx, (int32_t)nj, w, w, 1,
+                           Pd);
+        hipLaunchKernelGGL(k_sia_reduce, dim3((unsigned)nj), dim3(kBlock), 0, st, Pd, nbx, kSiaMax, 1, nr, small);
+        hipLaunchKernelGGL(k_sia_scale<R>, dim3(grid), dim3(kBlock), 0, st, V, vstride, Z, nbx, w, nr, small,
+                           Sm + (j * 2) * (m + 1), m + 1, rel2);
+      }
+      hipLaunchKernelGGL(k_sia_gram<R>, dim3(grid), dim3(kBlock), 0, st, V, vstride, Z, nbx, m, Pg, npair);
+      hipLaunchKernelGGL(k_sia_reduce, dim3((unsigned)nj), dim3(kBlock), 0, st, Pg, nbx * 4, npair, npair,
+                         Sm + 2 * m * (m + 1) + m, small);
+      HIPCHK(hipGetLastError());
+      HIPCHK(hipMemcpyAsync(hsmall.data(), Sm, (size_t)nj * small * 16, hipMemcpyDeviceToHost, st));
+      HIPCHK(hipStreamSynchronize(st));
+      std::vector<std::thread> th;
+      for (int q = 0; q < std::min<int64_t>(nth, nj); ++q)
+        th.emplace_back([&, q]() {
+          for (int64_t j = q; j < nj; j += nth)
+            sia_host_step(&hsmall[(size_t)j * small], m, spec.T, spec.kS, spec.kT, tol, rel2, jobs[j],
+                          &hg[(size_t)j * kSiaMax]);
+        });
+      for (auto &x : th) x.join();
+      for (auto &jb : jobs)
+        if (jb.failed || !std::isfinite(jb.phi) || !std::isfinite(jb.beta))
+          return fail(RP_ENOTCONV, "Arnoldi step control found no admissible step");
+      HIPCHK(hipMemcpyAsync(bG.p, hg.data(), (size_t)nj * kSiaMax * 16, hipMemcpyHostToDevice, st));
+      hipLaunchKernelGGL(k_sia_combine<R>, dim3(grid), dim3(kBlock), 0, st, V, vstride, Z, nbx, m,
+                         (const cx<double> *)bG.p);
+      HIPCHK(hipGetLastError());
+    }
+    std::vector<double> ph(nj);
+    for (int64_t j = 0; j < nj; ++j) ph[j] = jobs[j].phi;
+    if (op.flags & RP_FLAG_PROFILE)
+      for (auto &jb : jobs) {
+        g_prof.terms += (double)jb.steps * m;      // applications of A per job, summed
+        g_prof.quad_launches += (double)jb.steps;  // Arnoldi steps, summed over jobs
+      }
+    HIPCHK(hipMemcpyAsync(phi_out + j0, ph.data(), nj * 8, hipMemcpyHostToDevice, st));
+    HIPCHK(hipStreamSynchronize(st));
+  }
+  return RP_OK;
+}
+
 extern "C" int rp_propagate(const rp_system *sys, int32_t n_sys, const double *B_mT, int32_t nB,
                             const double *angles, int64_t M, const rp_opts *opts, double *phi, double *ps_t,
                             void *hip_stream) {
@@ -1704,6 +2210,23 @@ extern "C" int rp_propagate(const rp_system *sys, int32_t n_sys, const double *B
   if (!st) {
     HIPCHK(hipStreamCreate(&own.s));
     st = own.s;
+  }
+  if (op.flags & RP_FLAG_ARNOLDI) {   // short-iterative Arnoldi, one system at a time
+    if (op.flags & RP_FLAG_PROFILE) g_prof = Profile();
+    int64_t aoff = 0;
+    for (int i = 0; i < n_sys; ++i) {
+      const rp_system *s = &sys[i];
+      const int N = s->n_nuc[0] + s->n_nuc[1];
+      SystemSpec spec = tile_order(make_spec(s->n_nuc[0], s->n_nuc[1], s->two_I, s->a_mT, s->J_mT, s->kS, s->kT,
+                                             s->T_us, gamma_of(s)));
+      const double *ang = angles ? angles + aoff : nullptr;
+      double *out = phi + (int64_t)i * nB * M;
+      rc = op.precision == 64 ? sia_system<double>(spec, B_mT + (int64_t)i * nB, nB, ang, M, op, out, st)
+                              : sia_system<float>(spec, B_mT + (int64_t)i * nB, nB, ang, M, op, out, st);
+      if (rc) return rc;
+      aoff += M * N * 2;
+    }
+    return RP_OK;
   }
   EventLog log;
   log.on = (op.flags & RP_FLAG_PROFILE) != 0;

@@ -32,7 +32,7 @@ class _System(ctypes.Structure):
 class _Opts(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("init_mode", ctypes.c_int32), ("tol", ctypes.c_double),
                 ("rdt", ctypes.c_double), ("r_scale", ctypes.c_double), ("workspace_bytes", ctypes.c_int64),
-                ("flags", ctypes.c_int32), ("reserved", ctypes.c_int32), ("max_growth", ctypes.c_double)]
+                ("flags", ctypes.c_int32), ("krylov_dim", ctypes.c_int32), ("max_growth", ctypes.c_double)]
 
 
 _lib = None
@@ -45,6 +45,7 @@ RP_FLAG_TILED = 2
 RP_FLAG_XCD_LOCAL = 4
 RP_FLAG_XCD_SPREAD = 8
 RP_FLAG_NO_GRAPH = 16
+RP_FLAG_ARNOLDI = 32
 
 
 def lib():
@@ -103,10 +104,11 @@ class _CSystem:
         self.c.gamma = s.gamma if s.gamma else GAMMA_E
 
 
-def _opts(precision=64, init_mode=0, tol=0.0, rdt=0.0, r_scale=0.0, workspace_bytes=0, flags=0, max_growth=0.0):
+def _opts(precision=64, init_mode=0, tol=0.0, rdt=0.0, r_scale=0.0, workspace_bytes=0, flags=0, max_growth=0.0,
+          krylov_dim=0):
     o = _Opts()
     o.precision, o.init_mode, o.tol, o.rdt, o.r_scale = precision, init_mode, tol, rdt, r_scale
-    o.workspace_bytes, o.flags, o.reserved, o.max_growth = workspace_bytes, flags, 0, max_growth
+    o.workspace_bytes, o.flags, o.krylov_dim, o.max_growth = workspace_bytes, flags, krylov_dim, max_growth
     return o
 
 
@@ -136,7 +138,8 @@ def sample(system: SpinSystem, seed, M, first=0, stream_id=0, basis_mode=0, out=
 
 
 def propagate(systems, B_mT, angles, M, precision=64, init_mode=0, tol=0.0, rdt=0.0, r_scale=0.0,
-              workspace_bytes=0, out=None, profile=False, tiled=False, xcd=None, graph=True, max_growth=0.0):
+              workspace_bytes=0, out=None, profile=False, tiled=False, xcd=None, graph=True, max_growth=0.0,
+              arnoldi=False, krylov_dim=0):
     """rp_propagate: single-wavepacket yields [n_sys][nB][M] (float64 CUDA tensor).
 
     ``systems`` is a SpinSystem or a list; ``B_mT`` is [n_sys][nB] (host);
@@ -155,12 +158,12 @@ def propagate(systems, B_mT, angles, M, precision=64, init_mode=0, tol=0.0, rdt=
         out = torch.empty((len(systems), nB, M), dtype=torch.float64, device="cuda")
     ang = _dev_ptr(angles, torch.float64) if angles is not None and angles.numel() else None
     flags = (RP_FLAG_PROFILE if profile else 0) | (RP_FLAG_TILED if tiled else 0)
-    flags |= 0 if graph else RP_FLAG_NO_GRAPH
+    flags |= (0 if graph else RP_FLAG_NO_GRAPH) | (RP_FLAG_ARNOLDI if arnoldi else 0)
     if xcd == "local":
         flags |= RP_FLAG_XCD_LOCAL
     elif xcd == "spread":
         flags |= RP_FLAG_XCD_SPREAD
-    o = _opts(precision, init_mode, tol, rdt, r_scale, workspace_bytes, flags, max_growth)
+    o = _opts(precision, init_mode, tol, rdt, r_scale, workspace_bytes, flags, max_growth, krylov_dim)
     _check(lib().rp_propagate(arr, len(cs), B.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), nB, ang, M,
                               ctypes.byref(o), _dev_ptr(out, torch.float64), None, _stream(torch)))
     return out

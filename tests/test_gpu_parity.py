@@ -310,3 +310,33 @@ def test_strong_dissipation_matches_oracle(growth):
                 assert growth == 1e30 and e.code == -4, (i, prec, "basis", e)
                 continue
             assert _rel(phi, want_b) < tol, (i, prec, "basis", _rel(phi, want_b))
+
+
+# --------------------------------------------------------------------------- short-iterative Arnoldi
+@pytest.mark.parametrize("krylov", [0, 8, 32])
+def test_arnoldi_propagator_matches_oracle(krylov):
+    """The paper's propagator (RP_FLAG_ARNOLDI): adaptive Krylov steps with the in-step yield
+    from the projected singlet Gram matrix give the same per-sample yields as the oracle, for
+    spin-1 with exchange, strong triplet dissipation and a state spanning two workgroups."""
+    cases = [
+        (SpinSystem(2, 1, [1, 2, 1], [0.6, -0.3, 0.4], J_mT=0.5, kS=1.2, kT=0.4, T_us=1.0), False),
+        (SpinSystem(1, 0, [1], [0.5], kS=1.0, kT=300.0, T_us=0.05), False),
+        (SpinSystem(5, 4, [1] * 9, list(np.random.default_rng(9).normal(0, 0.5, 9)), kS=2.0, kT=0.5, T_us=0.3), True),
+    ]
+    for i, (s, sparse) in enumerate(cases):
+        B = np.array([[0.0, 2.0]])
+        ang = rp.sample(s, 60 + i, 3)
+        a_h = philox.sample_angles(60 + i, 0, 3, s.N)
+        want = gc.oracle_phi_sparse(s, B[0], a_h) if sparse else gc.oracle_phi(s, B[0], a_h)
+        for prec, tol in ((64, 1e-9), (32, 1e-5)):
+            _say(f"arnoldi case {i} precision {prec} krylov {krylov}")
+            phi = rp.propagate(s, B, ang, 3, precision=prec, arnoldi=True, krylov_dim=krylov).cpu().numpy()[0]
+            assert _rel(phi, want) < tol, (i, prec, krylov, _rel(phi, want))
+
+
+def test_arnoldi_invalid_krylov_dimension():
+    s = workloads.tiny_c1().systems[0]
+    ang = rp.sample(s, 1, 2)
+    for m in (1, 33, -2):
+        with pytest.raises(rp.RpError):
+            rp.propagate(s, np.array([[1.0]]), ang, 2, arnoldi=True, krylov_dim=m)
