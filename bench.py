@@ -447,7 +447,8 @@ def main():
                                f"{B.shape[1]} fields 0..10 mT x {Mb} samples per step",
                    "Z": s.Z, "dim": s.dim, "fields": int(B.shape[1]), "samples_per_step": Mb,
                    "precision": f"complex-FP{args.precision} state, FP64 coefficients and reductions",
-                   "launch": {"rdt": tuned["rdt"] or 80.0, "xcd": tuned["xcd"] or "default",
+                   "launch": {"rdt": tuned["rdt"] or 100.0,
+                              "xcd": tuned["xcd"] or "default",
                               "autotuned": bool(args.autotune)}},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": achieved / PEAK_HBM_GBS,

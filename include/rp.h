@@ -70,7 +70,7 @@ typedef struct rp_opts {
                                1: angles[..][0] holds the digit n = I - m per nucleus: the basis
                                state |S, M_1, M_2> of Eq. 12 (the [..][1] entry is ignored). */
   double tol;               /* Chebyshev truncation tolerance; 0 selects 1e-14 (64) or 1e-9 (32) */
-  double rdt;               /* target r*dt of one Chebyshev step (r = spectral half-width); 0 = 80 */
+  double rdt;               /* target r*dt of one Chebyshev step (r = spectral half-width); 0 = 100 */
   double r_scale;           /* multiplies the spectral half-width bound; 0 selects 1.  Values below 1
                                under-estimate the spectrum and exist to test RP_ENOTCONV. */
   int64_t workspace_bytes;  /* cap on device workspace per call; 0 selects half of free memory */

@@ -18,7 +18,7 @@ import numpy as np
 from . import rp
 
 DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "rpmc", "autotune.json")
-RDT = (60.0, 80.0, 120.0)
+RDT = (60.0, 80.0, 100.0, 120.0, 160.0)
 XCD = ("local", "spread")
 
 
