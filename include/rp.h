@@ -226,6 +226,18 @@ int rp_mlp_train_step(int32_t n_in, int32_t width, int32_t depth, float *params,
 int rp_profile_last(double *out, int32_t n);
 
 /*
+ * rp_combine -- per field, the inverse-variance weighted mean of two independent unbiased
+ * estimates of the same yield (Eq. 18 applied to two disjoint sample sets, e.g. the plain
+ * mean of the control variate's training yields and the control-variate estimate on the
+ * evaluation samples):  mean = (ma/ea^2 + mb/eb^2) / (1/ea^2 + 1/eb^2),  err = (1/ea^2 +
+ * 1/eb^2)^(-1/2); an estimate with zero error is taken as it is.  All arrays device [nB].
+ * The weights use estimated errors, so the combination carries a bias of relative order 1/M
+ * against the errors themselves.
+ */
+int rp_combine(const double *mean_a, const double *err_a, const double *mean_b, const double *err_b, int32_t nB,
+               double *mean, double *err, void *hip_stream);
+
+/*
  * rp_cv_beta -- per-field control-variate coefficient beta_b = Cov(phi, g) / Var(g) over the
  * M samples (the variance-minimising coefficient), from device phi, g [nB][M] to device
  * beta [nB] (0 where Var(g) = 0).  Take it from samples independent of the evaluation set.

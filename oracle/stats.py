@@ -32,3 +32,14 @@ def cv_mean_error(phi, g, mu, beta, mu_err=None):
     if mu_err is not None:
         e = np.sqrt(e * e + (beta[..., 0] * np.asarray(mu_err, float)) ** 2)
     return m, e
+
+
+def combine(mean_a, err_a, mean_b, err_b):
+    """Inverse-variance weighted mean of two independent unbiased estimates and its error:
+    the minimum-variance unbiased linear combination for fixed weights."""
+    ma, ea, mb, eb = (np.asarray(x, float) for x in (mean_a, err_a, mean_b, err_b))
+    va, vb = ea * ea, eb * eb
+    with np.errstate(divide="ignore", invalid="ignore"):
+        m = np.where(va == 0, ma, np.where(vb == 0, mb, (ma / va + mb / vb) / (1 / va + 1 / vb)))
+        e = np.where((va == 0) | (vb == 0), 0.0, 1 / np.sqrt(1 / va + 1 / vb))
+    return m, e

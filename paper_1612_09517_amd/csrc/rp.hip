@@ -887,6 +887,23 @@ __global__ __launch_bounds__(256) void k_stats(StatArgs a) {
   }
 }
 
+// Inverse-variance combination of two independent unbiased estimates per field.
+__global__ __launch_bounds__(256) void k_combine(const double *ma, const double *ea, const double *mb,
+                                                 const double *eb, int32_t nB, double *mean, double *err) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= nB) return;
+  const double va = ea[b] * ea[b], vb = eb[b] * eb[b];
+  if (va == 0.0 || vb == 0.0) {   // an exact estimate wins outright
+    const bool a_exact = va == 0.0;
+    mean[b] = a_exact ? ma[b] : mb[b];
+    err[b] = 0.0;
+    return;
+  }
+  const double wa = 1.0 / va, wb = 1.0 / vb;
+  mean[b] = (wa * ma[b] + wb * mb[b]) / (wa + wb);
+  err[b] = 1.0 / sqrt(wa + wb);
+}
+
 // Per-field beta = Cov(phi, g) / Var(g) (two passes: means, then centred sums).
 struct BetaArgs {
   const double *phi, *g;
@@ -2308,6 +2325,18 @@ extern "C" int rp_cv_beta(const double *phi, const double *g, int32_t nB, int64_
   if (!phi || !g || !beta) return fail(RP_EINVAL, "null pointer");
   BetaArgs a{phi, g, beta, M};
   hipLaunchKernelGGL(k_beta, dim3(nB), dim3(256), 0, (hipStream_t)hip_stream, a);
+  HIPCHK(hipGetLastError());
+  return RP_OK;
+}
+
+extern "C" int rp_combine(const double *mean_a, const double *err_a, const double *mean_b, const double *err_b,
+                          int32_t nB, double *mean, double *err, void *hip_stream) {
+  g_err.clear();
+  if (nB < 0) return fail(RP_EINVAL, "negative count");
+  if (nB == 0) return RP_OK;
+  if (!mean_a || !err_a || !mean_b || !err_b || !mean || !err) return fail(RP_EINVAL, "null pointer");
+  hipLaunchKernelGGL(k_combine, dim3(grid1(nB)), dim3(256), 0, (hipStream_t)hip_stream, mean_a, err_a, mean_b, err_b,
+                     nB, mean, err);
   HIPCHK(hipGetLastError());
   return RP_OK;
 }

@@ -13,7 +13,9 @@ For one system and its field sweep:
 4. mu_B = mean of g over K fresh directions of stream 2 (rp_mlp_forward, rp_yield), with its
    standard error;
 5. estimate: rp_yield(phi, g, mu, beta, err mu) on the evaluation samples, i.e.
-   mean(phi - beta (g - mu)), unbiased because g, beta and mu do not depend on them.
+   mean(phi - beta (g - mu)), unbiased because g, beta and mu do not depend on them;
+   optionally combined by rp_combine with the plain mean of the training yields, which are
+   independent Monte Carlo samples of the same yield (stream 1).
 
 Every numerical step of the method runs in librp kernels; this module moves device buffers
 between calls, standardises the training targets on the host, picks batches and keeps the
@@ -127,6 +129,9 @@ class ControlVariate:
         g_va = y.double().reshape(n_val, nB).t().contiguous()
         phi_va = phi[rows_tr:].reshape(n_val, nB).t().contiguous()
         self.beta = rp.cv_beta(phi_va, g_va)
+        # The training yields are also plain Monte Carlo samples (stream 1, independent of the
+        # evaluation stream): their per-field mean is a second unbiased estimate.
+        self.train_mean, self.train_err = rp.yield_stats(phi.reshape(n_pf, nB).t().contiguous())
         return best
 
     def fit_mu(self, K, first=0):
@@ -136,7 +141,12 @@ class ControlVariate:
         return self.mu, self.mu_err
 
     # ------------------------------------------------------------------ estimate
-    def estimate(self, angles, phi):
-        """Control-variate mean and standard error per field for evaluation samples."""
+    def estimate(self, angles, phi, with_training=False):
+        """Control-variate mean and standard error per field for evaluation samples; with
+        ``with_training`` combined (inverse-variance weights) with the plain mean of the
+        training yields."""
         g = self.g(angles)
-        return rp.yield_stats(phi, g, self.mu, self.beta, self.mu_err)
+        m, e = rp.yield_stats(phi, g, self.mu, self.beta, self.mu_err)
+        if with_training:
+            m, e = rp.combine(m, e, self.train_mean, self.train_err)
+        return m, e

@@ -39,7 +39,7 @@ _lib = None
 
 EXPORTS = ["rp_sample", "rp_propagate", "rp_yield", "rp_strerror", "rp_last_error", "rp_bessel_j",
            "rp_plan_field", "rp_profile_last", "rp_mlp_param_count", "rp_mlp_workspace_floats",
-           "rp_mlp_features", "rp_mlp_forward", "rp_mlp_train_step", "rp_cv_beta"]
+           "rp_mlp_features", "rp_mlp_forward", "rp_mlp_train_step", "rp_cv_beta", "rp_combine"]
 RP_FLAG_PROFILE = 1
 RP_FLAG_TILED = 2
 RP_FLAG_XCD_LOCAL = 4
@@ -68,6 +68,7 @@ def lib():
         L.rp_mlp_workspace_floats.restype = i64
         L.rp_mlp_features.argtypes = [vp, i64, i32, vp, i32, i32, i32, vp, vp]
         L.rp_cv_beta.argtypes = [vp, vp, i32, i64, vp, vp]
+        L.rp_combine.argtypes = [vp, vp, vp, vp, i32, vp, vp, vp]
         L.rp_mlp_forward.argtypes = [i32, i32, i32, vp, vp, i64, vp, vp, vp]
         L.rp_mlp_train_step.argtypes = [i32, i32, i32, vp, vp, vp, i64, vp, vp, i64, ctypes.c_float, vp, vp,
                                         vp, vp]
@@ -78,7 +79,7 @@ def lib():
         L.rp_plan_field.argtypes = [sp, ctypes.c_double, op, dp, dp, dp]
         L.rp_profile_last.argtypes = [dp, i32]
         for f in ("rp_sample", "rp_propagate", "rp_yield", "rp_bessel_j", "rp_plan_field", "rp_profile_last",
-                  "rp_mlp_features", "rp_mlp_forward", "rp_mlp_train_step", "rp_cv_beta"):
+                  "rp_mlp_features", "rp_mlp_forward", "rp_mlp_train_step", "rp_cv_beta", "rp_combine"):
             getattr(L, f).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -167,6 +168,18 @@ def propagate(systems, B_mT, angles, M, precision=64, init_mode=0, tol=0.0, rdt=
     _check(lib().rp_propagate(arr, len(cs), B.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), nB, ang, M,
                               ctypes.byref(o), _dev_ptr(out, torch.float64), None, _stream(torch)))
     return out
+
+
+def combine(mean_a, err_a, mean_b, err_b):
+    """rp_combine: inverse-variance combination of two independent per-field estimates (CUDA float64 [nB])."""
+    import torch
+    nB = mean_a.numel()
+    mean = torch.empty(nB, dtype=torch.float64, device="cuda")
+    err = torch.empty(nB, dtype=torch.float64, device="cuda")
+    _check(lib().rp_combine(_dev_ptr(mean_a.contiguous(), torch.float64), _dev_ptr(err_a.contiguous(), torch.float64),
+                            _dev_ptr(mean_b.contiguous(), torch.float64), _dev_ptr(err_b.contiguous(), torch.float64),
+                            nB, _dev_ptr(mean, torch.float64), _dev_ptr(err, torch.float64), _stream(torch)))
+    return mean, err
 
 
 def yield_stats(phi, cv_g=None, cv_mu=None, cv_beta=None, cv_mu_err=None):

@@ -142,3 +142,10 @@ def test_control_variate_is_unbiased_and_reduces_variance():
     wm, we = stats.cv_mean_error(phi_ev.cpu().numpy(), g, c.mu.cpu().numpy(), c.beta.cpu().numpy(),
                                  c.mu_err.cpu().numpy())
     assert np.max(np.abs(wm - m_cv)) < 1e-12 and np.max(np.abs(we - e_cv)) < 1e-12
+    # combined with the plain mean of the (independent) training yields
+    m_cb, e_cb = (t.cpu().numpy() for t in c.estimate(a_ev, phi_ev, with_training=True))
+    assert np.all(np.abs(m_cb - exact) < 4 * e_cb + 1e-5)
+    assert np.all(e_cb < e_cv)
+    tm, te = c.train_mean.cpu().numpy(), c.train_err.cpu().numpy()
+    om, oe = stats.combine(m_cv, e_cv, tm, te)
+    assert np.max(np.abs(om - m_cb)) < 1e-12 and np.max(np.abs(oe - e_cb)) < 1e-12

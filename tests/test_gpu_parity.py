@@ -340,3 +340,15 @@ def test_arnoldi_invalid_krylov_dimension():
     for m in (1, 33, -2):
         with pytest.raises(rp.RpError):
             rp.propagate(s, np.array([[1.0]]), ang, 2, arnoldi=True, krylov_dim=m)
+
+
+def test_combine_matches_oracle():
+    rng = np.random.default_rng(5)
+    ma, mb = rng.uniform(0, 1, 37), rng.uniform(0, 1, 37)
+    ea, eb = rng.uniform(1e-4, 1e-2, 37), rng.uniform(1e-4, 1e-2, 37)
+    ea[3] = 0.0
+    eb[7] = 0.0
+    t = lambda x: torch.tensor(x, dtype=torch.float64, device="cuda")
+    m, e = rp.combine(t(ma), t(ea), t(mb), t(eb))
+    wm, we = stats.combine(ma, ea, mb, eb)
+    assert np.max(np.abs(m.cpu().numpy() - wm)) < 1e-14 and np.max(np.abs(e.cpu().numpy() - we)) < 1e-14

@@ -310,6 +310,14 @@ def test_table_I_effective_hyperfine_fields():
     assert sysd.Z == 1048576                                         # Z quoted in Sec. V
 
 
+def test_stats_combine_closed_forms():
+    """Inverse-variance combination: equal errors average with err/sqrt2; weights 1 and 1/4
+    give (1 + 3/4)/(5/4); an exact estimate is taken as it is."""
+    m, e = stats.combine([0.2, 1.0, 0.4], [0.1, 1.0, 0.0], [0.4, 3.0, 0.9], [0.1, 2.0, 0.3])
+    assert np.allclose(m, [0.3, 1.4, 0.4], rtol=0, atol=1e-15)
+    assert np.allclose(e, [0.1 / np.sqrt(2), 1 / np.sqrt(1.25), 0.0], rtol=0, atol=1e-15)
+
+
 def test_stats_eq23():
     phi = np.array([[0.1, 0.3, 0.2, 0.6]])
     m, e = stats.mc_mean_error(phi)
