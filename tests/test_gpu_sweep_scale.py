@@ -80,11 +80,12 @@ def test_streaming_hints_leave_results_unchanged():
         assert abs(big[0, 0, 0] - want) < tol * want, (prec, big[0, 0, 0], want)
 
 
-@pytest.mark.parametrize("name", ["paper", "large"])
+@pytest.mark.parametrize("name", ["paper", "large", "large_full"])
 def test_full_size_short_horizon_against_oracle_golden(name):
     """The two largest states at their full size (the Sec. IV model, Z = 2^20, and the spin-1
-    workload, Z = 2,985,984) on a horizon shortened to a few Chebyshev steps, against yields
-    the oracle computed one by one (tests/golden/make_paper_golden.py, make_large_golden.py)."""
+    workload, Z = 2,985,984) on a horizon shortened to a few Chebyshev steps -- and the spin-1
+    workload on its own horizon, T = 10 us -- against yields the oracle computed one by one
+    (tests/golden/make_paper_golden.py, make_large_golden.py [--full])."""
     import dataclasses
     g = json.load(open(os.path.join(os.path.dirname(__file__), "golden", f"{name}_golden.json")))
     w = workloads.paper_model() if name == "paper" else workloads.large_c4()
