@@ -123,7 +123,7 @@ def cv_headline(args):
     sync()
     t_gen = time.perf_counter() - t0
     t0 = time.perf_counter()
-    val = c.train(a_tr, phi_tr, epochs=args.cv_epochs, batch=512, lr=1e-3)
+    val = c.train(a_tr, phi_tr, epochs=args.cv_epochs, batch=512, lr=1e-3, augment=not args.cv_no_augment)
     sync()
     t_train = time.perf_counter() - t0
     say(f"trained: validation mse {val:.4f} (standardised), {len(c.history)} epochs")
@@ -165,7 +165,8 @@ def cv_headline(args):
            "value": wall_cv, "unit": "s", "higher_is_better": False, "n_gpus": 1, "data": "synthetic",
            "dtype": "f32", "config": {"workload": w.name + ": N=14 spin-1/2, Z=16384, 32 fields 0..5 mT",
                                       "kS": s.kS, "kT": s.kT, "T_us": s.T_us, "train_yields": n_train * nB,
-                                      "eval_samples": Me, "mu_samples": args.cv_quad, "net": "3x256 GELU, BF16 MFMA"},
+                                      "eval_samples": Me, "mu_samples": args.cv_quad, "net": "3x256 GELU, BF16 MFMA",
+                                      "augment": not args.cv_no_augment, "epochs_run": len(c.history)},
            "plain_fp64_wall_s": wall64, "plain_fp32_wall_s": wall32, "speedup_vs_fp64": wall64 / wall_cv,
            "cv_without_training_mean_wall_s": wall_cv_only,
            "rate_fp32_props_s": rate32, "rate_fp64_props_s": rate64,
@@ -351,7 +352,8 @@ def main():
     ap.add_argument("--cv", action="store_true",
                     help="headline comparison: FP32 + learned control variate vs plain FP64 sweep wall time")
     ap.add_argument("--cv-train", type=int, default=4096, help="training yields (one direction each)")
-    ap.add_argument("--cv-epochs", type=int, default=60)
+    ap.add_argument("--cv-epochs", type=int, default=200)
+    ap.add_argument("--cv-no-augment", action="store_true", help="train without the field-axis rotations")
     ap.add_argument("--cv-quad", type=int, default=65536, help="samples for the mean of the network")
     ap.add_argument("--cv-eval", type=int, default=128, help="evaluation samples (pilot)")
     ap.add_argument("--summarize", default="",

@@ -189,6 +189,11 @@ int rp_yield(const double *phi, int32_t nB, int64_t M, const double *cv_g, const
  *                        layout 0: [M][N][2] angles shared by all fields, row = b*M + s;
  *                        layout 1: the same angles, row = s*nB + b (batches mix fields);
  *                        layout 2: [nB*M][N][2] angles, one per row, row r has field r % nB.
+ *                        rot_seed != 0 advances every azimuth of row r by 2 pi u_r, u_r from
+ *                        SplitMix64(rot_seed + (r+1) * 0x9E3779B97F4A7C15) (top 53 bits +
+ *                        1/2, times 2^-53): a common rotation of the nuclear directions about
+ *                        the field, under which the yield is exactly invariant (training-data
+ *                        augmentation; 0 for inference).
  * rp_mlp_forward         y[rows] = g(x) (device).
  * rp_mlp_train_step      one Adam step (beta1 0.9, beta2 0.999, eps 1e-8; step >= 1 is the
  *                        Adam time step) on the batch (x, target); optional device outputs:
@@ -199,7 +204,7 @@ int rp_yield(const double *phi, int32_t nB, int64_t M, const double *cv_g, const
 int64_t rp_mlp_param_count(int32_t n_in, int32_t width, int32_t depth);
 int64_t rp_mlp_workspace_floats(int32_t n_in, int32_t width, int32_t depth, int64_t rows);
 int rp_mlp_features(const double *angles, int64_t M, int32_t N, const double *B_mT, int32_t nB,
-                    int32_t n_in_pad, int32_t layout, float *x, void *hip_stream);
+                    int32_t n_in_pad, int32_t layout, uint64_t rot_seed, float *x, void *hip_stream);
 int rp_mlp_forward(int32_t n_in, int32_t width, int32_t depth, const float *params, const float *x,
                    int64_t rows, float *y, float *workspace, void *hip_stream);
 int rp_mlp_train_step(int32_t n_in, int32_t width, int32_t depth, float *params, float *adam_m,

@@ -59,18 +59,33 @@ def init_params(n_in, width, depth, rng):
     return np.concatenate(parts)
 
 
-def features(angles, B_mT):
-    """Rows field-major: row b*M + s."""
+def splitmix_unit(seed, r):
+    """u in (0, 1) from SplitMix64 (Steele, Lea & Flood 2014) of seed + (r + 1) * golden gamma:
+    the top 53 bits plus one half, times 2^-53."""
+    mask = (1 << 64) - 1
+    z = (seed + (r + 1) * 0x9E3779B97F4A7C15) & mask
+    z = ((z ^ (z >> 30)) * 0xBF58476D1CE4E5B9) & mask
+    z = ((z ^ (z >> 27)) * 0x94D049BB133111EB) & mask
+    z ^= z >> 31
+    return ((z >> 11) + 0.5) * 2.0 ** -53
+
+
+def features(angles, B_mT, rot_seed=0):
+    """Rows field-major: row b*M + s.  rot_seed != 0 advances every azimuth of row r by
+    2 pi u_r (a common rotation of the nuclear directions about the field axis)."""
     angles = np.asarray(angles, float)
     M, N = angles.shape[0], angles.shape[1]
     B = np.atleast_1d(np.asarray(B_mT, float))
     x = np.zeros((len(B) * M, in_pad(3 * N + 1)))
-    ct, ph = angles[:, :, 0], angles[:, :, 1]
-    st = np.sqrt(np.maximum(0.0, 1.0 - ct * ct))
-    n = np.stack([st * np.cos(ph), st * np.sin(ph), ct], axis=2).reshape(M, 3 * N)
     for b, Bv in enumerate(B):
-        x[b * M:(b + 1) * M, :3 * N] = n
-        x[b * M:(b + 1) * M, 3 * N] = np.log(abs(Bv) + 0.05)
+        for s in range(M):
+            r = b * M + s
+            ct, ph = angles[s, :, 0], angles[s, :, 1].copy()
+            if rot_seed:
+                ph = ph + 2.0 * np.pi * splitmix_unit(rot_seed, r)
+            st = np.sqrt(np.maximum(0.0, 1.0 - ct * ct))
+            x[r, :3 * N] = np.stack([st * np.cos(ph), st * np.sin(ph), ct], axis=1).reshape(3 * N)
+            x[r, 3 * N] = np.log(abs(Bv) + 0.05)
     return x
 
 

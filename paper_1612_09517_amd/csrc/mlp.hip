@@ -160,13 +160,26 @@ __global__ __launch_bounds__(256) void k_adam(AdamArgs a) {
 }
 
 // Features of (sample, field): the unit vectors n(Omega_k) (Eq. 16) of every nucleus and
-// log(B/mT + 0.05); rows ordered field-major, zero padded to n_in_pad columns.
+// log(B/mT + 0.05); rows ordered field-major, zero padded to n_in_pad columns.  With a nonzero
+// rot_seed every azimuth of row r is advanced by the same angle 2 pi u_r: a rotation of all
+// nuclear directions about the field axis, under which the yield is invariant (H, P_S and the
+// singlet commute with the total J_z), used to augment training data.
 struct FeatArgs {
   const double *angles, *B;
   float *x;
   int64_t M;
   int32_t N, nB, n_in_pad, layout;
+  uint64_t rot_seed;
 };
+
+// u in (0, 1) from SplitMix64 (Steele, Lea & Flood 2014) of seed + (r + 1) * golden gamma.
+__device__ __forceinline__ double splitmix_unit(uint64_t seed, uint64_t r) {
+  uint64_t z = seed + (r + 1) * 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  z ^= z >> 31;
+  return ((double)(z >> 11) + 0.5) * 0x1.0p-53;
+}
 
 __global__ __launch_bounds__(256) void k_features(FeatArgs f) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -179,7 +192,9 @@ __global__ __launch_bounds__(256) void k_features(FeatArgs f) {
   float v = 0.f;
   if (c < 3 * f.N) {
     const int k = c / 3, q = c - 3 * k;
-    const double ct = f.angles[(s * f.N + k) * 2], ph = f.angles[(s * f.N + k) * 2 + 1];
+    const double ct = f.angles[(s * f.N + k) * 2];
+    double ph = f.angles[(s * f.N + k) * 2 + 1];
+    if (f.rot_seed) ph += 6.283185307179586 * splitmix_unit(f.rot_seed, (uint64_t)r);
     const double st = sqrt(fmax(0.0, 1.0 - ct * ct));
     v = (float)(q == 0 ? st * cos(ph) : q == 1 ? st * sin(ph) : ct);
   } else if (c == 3 * f.N) {
@@ -265,12 +280,12 @@ extern "C" int64_t rp_mlp_workspace_floats(int32_t n_in, int32_t width, int32_t 
 }
 
 extern "C" int rp_mlp_features(const double *angles, int64_t M, int32_t N, const double *B_mT, int32_t nB,
-                               int32_t n_in_pad, int32_t layout, float *x, void *hip_stream) {
+                               int32_t n_in_pad, int32_t layout, uint64_t rot_seed, float *x, void *hip_stream) {
   if (M < 0 || N < 0 || nB < 0 || n_in_pad < 3 * N + 1) return mlp_fail(RP_EINVAL, "bad feature sizes");
   if (layout < 0 || layout > 2) return mlp_fail(RP_EINVAL, "layout must be 0, 1 or 2");
   if (M == 0 || nB == 0) return RP_OK;
   if (!angles || !B_mT || !x) return mlp_fail(RP_EINVAL, "null pointer");
-  FeatArgs f{angles, B_mT, x, M, N, nB, n_in_pad, layout};
+  FeatArgs f{angles, B_mT, x, M, N, nB, n_in_pad, layout, rot_seed};
   hipLaunchKernelGGL(k_features, dim3(blocks((int64_t)nB * M * n_in_pad)), dim3(256), 0,
                      (hipStream_t)hip_stream, f);
   return hipGetLastError() == hipSuccess ? RP_OK : mlp_fail(RP_EDEVICE, "feature kernel launch failed");

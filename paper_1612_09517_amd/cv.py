@@ -8,6 +8,8 @@ For one system and its field sweep:
 2. training: the network g(Omega, B) of rp_mlp_* fitted by Adam on mean squared error of
    targets standardised per field (the fit then measures within-field fluctuations, the
    part a control variate can remove), the last 10 % of yields held out for early stopping;
+   each epoch rotates every training direction set about the field axis by a fresh angle,
+   a symmetry of the yield (H, P_S and the singlet commute with the total J_z);
 3. beta_B = Cov(phi, g)/Var(g) per field on the held-out yields (rp_cv_beta); beta absorbs the
    per-field scale of g;
 4. mu_B = mean of g over K fresh directions of stream 2 (rp_mlp_forward, rp_yield), with its
@@ -87,9 +89,11 @@ class ControlVariate:
         return y.double().reshape(self.nB, M)
 
     # ------------------------------------------------------------------ training
-    def train(self, angles, phi, epochs=60, batch=512, lr=1e-3, val_frac=0.1, patience=10):
+    def train(self, angles, phi, epochs=200, batch=512, lr=1e-3, val_frac=0.1, patience=10, augment=True):
         """Fits g on training data from generate_training; returns the best validation MSE in
-        units of the per-field variance (1 - R^2 within fields)."""
+        units of the per-field variance (1 - R^2 within fields).  With ``augment`` every epoch
+        sees each training direction set rotated about the field axis by a fresh random angle
+        (the yield is invariant under that rotation; rp_mlp_features rot_seed)."""
         import torch
         nB = self.nB
         n_pf = phi.shape[0] // nB
@@ -109,9 +113,13 @@ class ControlVariate:
         ws = rp.mlp_workspace(self.n_in, self.width, self.depth, max(batch, x_va.shape[0]))
         best, best_p, bad = np.inf, self.params.clone(), 0
         for ep in range(epochs):
+            x_ep = x_tr
+            if augment:
+                x_ep = rp.mlp_features(angles, self.B, self.n_in, layout=2,
+                                       rot_seed=(self.seed << 20) + ep + 1)[:rows_tr]
             for i in range(0, rows_tr - batch + 1, batch):
                 self.step += 1
-                rp.mlp_train_step(self.params, self.m, self.v, self.step, x_tr[i:i + batch], t_tr[i:i + batch],
+                rp.mlp_train_step(self.params, self.m, self.v, self.step, x_ep[i:i + batch], t_tr[i:i + batch],
                                   self.n_in, self.width, self.depth, lr=lr, workspace=ws)
             y = rp.mlp_forward(self.params, x_va, self.n_in, self.width, self.depth, workspace=ws)
             val = float(np.mean((y.cpu().numpy() - t_va_h) ** 2))

@@ -66,7 +66,7 @@ def lib():
         L.rp_mlp_param_count.restype = i64
         L.rp_mlp_workspace_floats.argtypes = [i32, i32, i32, i64]
         L.rp_mlp_workspace_floats.restype = i64
-        L.rp_mlp_features.argtypes = [vp, i64, i32, vp, i32, i32, i32, vp, vp]
+        L.rp_mlp_features.argtypes = [vp, i64, i32, vp, i32, i32, i32, u64, vp, vp]
         L.rp_cv_beta.argtypes = [vp, vp, i32, i64, vp, vp]
         L.rp_combine.argtypes = [vp, vp, vp, vp, i32, vp, vp, vp]
         L.rp_mlp_forward.argtypes = [i32, i32, i32, vp, vp, i64, vp, vp, vp]
@@ -216,8 +216,9 @@ def mlp_workspace(n_in, width, depth, rows):
     return torch.empty(max(n, 1), dtype=torch.float32, device="cuda")
 
 
-def mlp_features(angles, B_mT, n_in, layout=0):
-    """rp_mlp_features: [nB*M][n_in_pad] float32 features (row layouts 0, 1, 2 of rp.h)."""
+def mlp_features(angles, B_mT, n_in, layout=0, rot_seed=0):
+    """rp_mlp_features: [nB*M][n_in_pad] float32 features (row layouts 0, 1, 2 of rp.h); a
+    nonzero rot_seed rotates each row's directions about the field axis (augmentation)."""
     import torch
     B = torch.as_tensor(np.asarray(B_mT, np.float64).reshape(-1), device="cuda")
     nB = B.numel()
@@ -225,7 +226,7 @@ def mlp_features(angles, B_mT, n_in, layout=0):
     M = angles.shape[0] // nB if layout == 2 else angles.shape[0]
     x = torch.empty((nB * M, mlp_in_pad(n_in)), dtype=torch.float32, device="cuda")
     _check(lib().rp_mlp_features(_dev_ptr(angles.contiguous(), torch.float64), M, N, _dev_ptr(B, torch.float64),
-                                 nB, x.shape[1], int(layout), _dev_ptr(x, torch.float32),
+                                 nB, x.shape[1], int(layout), int(rot_seed), _dev_ptr(x, torch.float32),
                                  _stream(torch)))
     return x
 

@@ -52,6 +52,15 @@ def test_features_match_oracle(layout):
     assert np.max(np.abs(x - want)) < 1e-6
 
 
+def test_rotated_features_match_oracle():
+    B = [0.0, 1.5, 4.0]
+    ang = philox.sample_angles(6, 0, 41, 6)
+    x = rp.mlp_features(_t(ang, torch.float64), B, 19, layout=0, rot_seed=987654321).cpu().numpy()
+    assert np.max(np.abs(x - mlp.features(ang, B, rot_seed=987654321))) < 1e-6
+    x0 = rp.mlp_features(_t(ang, torch.float64), B, 19, layout=0).cpu().numpy()
+    assert np.max(np.abs(x - x0)) > 0.1          # the rotation did act
+
+
 def _net(n_in=19, width=64, depth=3, seed=1):
     rng = np.random.default_rng(seed)
     p = mlp.init_params(n_in, width, depth, rng)

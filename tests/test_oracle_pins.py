@@ -197,6 +197,30 @@ def test_trace_even_in_field():
                    - yields.FieldOracle(s, -B, 3.0).trace_yield()) < 1e-12
 
 
+def test_yield_invariant_under_common_rotation_about_field():
+    """H (Eq. 1, field along z, isotropic couplings), P_S and the singlet commute with the
+    total J_z, so rotating every nuclear direction about z by the same angle leaves each
+    single-wavepacket yield unchanged (the symmetry the control variate's training uses)."""
+    d = spin.DenseSystem((2, 1), [1, 2, 1], [0.7, -0.4, 0.3], J_mT=0.6, kS=1.7, kT=0.4)
+    fo = yields.FieldOracle(d, 2.0, 3.0)
+    for a in philox.sample_angles(8, 0, 3, 3):
+        y0 = fo.phi(coherent.initial_wavepacket(d, a))
+        r = a.copy()
+        r[:, 1] += 1.234
+        assert abs(fo.phi(coherent.initial_wavepacket(d, r)) - y0) < 1e-12
+        q = a.copy()
+        q[0, 1] += 1.234                           # one nucleus alone: not a symmetry
+        assert abs(fo.phi(coherent.initial_wavepacket(d, q)) - y0) > 1e-6
+
+
+def test_splitmix_unit_reference_values():
+    """SplitMix64 (Steele, Lea & Flood 2014): the first outputs of the reference generator
+    seeded with 0 are 0xE220A8397B1DCDAF, 0x6E789E6AA1B965F4, 0x06C45D188009454F."""
+    from oracle import mlp as omlp
+    for r, word in enumerate((0xE220A8397B1DCDAF, 0x6E789E6AA1B965F4, 0x06C45D188009454F)):
+        assert omlp.splitmix_unit(0, r) == ((word >> 11) + 0.5) * 2.0 ** -53
+
+
 def test_yield_bounds_and_initial_values():
     s = _random_system()
     fo = yields.FieldOracle(s, 1.1, 6.0)
