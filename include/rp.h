@@ -146,7 +146,13 @@ int rp_sample(const rp_system *s, uint64_t seed, uint32_t stream_id, uint64_t fi
  * Each wavepacket is propagated by a Chebyshev expansion of exp(-iGt),
  * G = H - iK, in steps of length dt; the time integral of P_S within each step
  * is exact up to the truncation tolerance (Gauss-Legendre integrals of products
- * of Bessel functions, factored by pivoted Cholesky).
+ * of Bessel functions, factored by pivoted Cholesky).  With RP_FLAG_ARNOLDI the
+ * short-iterative Arnoldi propagator is used instead (see that flag).
+ *
+ * Workspace: the call allocates device memory for its chunk of wavepackets (three
+ * vectors of 4Z complex numbers per job plus the singlet amplitudes of one step,
+ * N_terms x Z per job), at most opts->workspace_bytes or half of the free memory,
+ * and frees it before returning.
  */
 int rp_propagate(const rp_system *sys, int32_t n_sys, const double *B_mT, int32_t nB,
                  const double *angles, int64_t M, const rp_opts *opts, double *phi, double *ps_t,
