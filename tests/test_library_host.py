@@ -138,3 +138,19 @@ def test_argument_validation_without_device():
     assert L.rp_yield(fake, 3, 4, fake, None, None, None, fake, fake, None) == rp.RP_EINVAL
     assert b"two_I" in L.rp_last_error() or len(L.rp_last_error()) > 0
     assert L.rp_strerror(rp.RP_ENOTCONV).startswith(b"propagation")
+
+
+def test_autotune_cache_hit_needs_no_probe(tmp_path):
+    """A cached entry for the system's shape is returned as it is (no timed probes, so no
+    device is needed); the key carries the precision, the spins per radical and the spectral
+    scale, so another precision misses."""
+    import json
+    from paper_1612_09517_amd import autotune
+    s = _sys(kS=2.0, kT=0.5)
+    B = [0.0, 2.0, 4.0]
+    r_max = max(rp.plan_field(s, b, precision=32)["r"] for b in (0.0, 4.0))
+    key = autotune._key(s, 32, r_max)
+    cache = tmp_path / "tune.json"
+    cache.write_text(json.dumps({key: {"best": {"rdt": 120.0, "xcd": "spread"}, "probes": []}}))
+    assert autotune.tune(s, B, precision=32, cache=str(cache)) == {"rdt": 120.0, "xcd": "spread"}
+    assert autotune._key(s, 64, r_max) != key
