@@ -351,7 +351,7 @@ def main():
     ap.add_argument("--max-n", type=int, default=12, help="batched workload: only systems with at most this many nuclei")
     ap.add_argument("--cv", action="store_true",
                     help="headline comparison: FP32 + learned control variate vs plain FP64 sweep wall time")
-    ap.add_argument("--cv-train", type=int, default=4096, help="training yields (one direction each)")
+    ap.add_argument("--cv-train", type=int, default=3072, help="training yields (one direction each)")
     ap.add_argument("--cv-epochs", type=int, default=200)
     ap.add_argument("--cv-no-augment", action="store_true", help="train without the field-axis rotations")
     ap.add_argument("--cv-quad", type=int, default=65536, help="samples for the mean of the network")
