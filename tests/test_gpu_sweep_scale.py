@@ -130,3 +130,20 @@ def test_zero_couplings_large_mixed_radix_closed_form():
         print("zero couplings: precision", prec, flush=True)
         phi = rp.propagate(s, np.array([[0.7, 3.0]]), ang, 1, precision=prec).cpu().numpy()[0]
         assert np.max(np.abs(phi - want)) < tol, (prec, phi, want)
+
+
+def test_paper_model_full_horizon_fp32_tracks_fp64():
+    """The Sec. IV model on its own horizon (T = 14/kS, strong triplet dissipation): complex
+    FP32 with its default growth bound tracks FP64 per yield, and the yield dips near
+    omega = 2J (Sec. IV) for these samples."""
+    w = workloads.paper_model()
+    s = w.systems[0]
+    B = np.array([[0.0, 3.5, 9.0]])
+    ang = rp.sample(s, w.seed, 2)
+    print("paper model full horizon", flush=True)
+    p64 = rp.propagate(s, B, ang, 2, precision=64).cpu().numpy()[0]
+    p32 = rp.propagate(s, B, ang, 2, precision=32).cpu().numpy()[0]
+    assert np.max(np.abs(p32 - p64) / p64) < 1e-5
+    assert np.all((p64 > 0) & (p64 < 1))
+    m = p64.mean(axis=1)
+    assert m[1] < m[0] and m[1] < m[2]
