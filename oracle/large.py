@@ -87,13 +87,3 @@ def yield_augmented(system, B_mT, T, psi0, tau=1.0):
         psi, chi = w[:n], w[n:]
         total += float(np.real(np.vdot(psi, chi)))
     return system.kS * total, psi
-
-
-def trajectory(system, B_mT, psi0, times):
-    """(P_S(t), N(t)) for the wavepacket at the given times (library expm action)."""
-    G = system.G(B_mT)
-    out = expm_multiply(-1j * G, np.asarray(psi0, complex), start=times[0], stop=times[-1],
-                        num=len(times), endpoint=True)
-    ps = np.array([np.real(np.vdot(v, system.PS @ v)) for v in out])
-    nn = np.array([np.real(np.vdot(v, v)) for v in out])
-    return ps, nn
