@@ -208,14 +208,24 @@ def other_workload(args):
     for _ in range(args.warmup):
         rp.propagate(systems, B, cat, M, precision=args.precision)
     torch.cuda.synchronize()
+    # Long single-system sweeps run a few fields per call and report each call.
+    group = args.field_group if (args.field_group > 0 and len(systems) == 1) else B.shape[1]
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        phi = rp.propagate(systems, B, cat, M, precision=args.precision)
+        parts = []
+        for f0 in range(0, B.shape[1], group):
+            parts.append(rp.propagate(systems, B[:, f0:f0 + group], cat, M, precision=args.precision))
+            if group < B.shape[1]:
+                torch.cuda.synchronize()
+                print(json.dumps({"progress": f"fields {f0 + len(B[0, f0:f0 + group])}/{B.shape[1]}",
+                                  "t_s": round(time.perf_counter() - t0, 1)}), flush=True)
+        phi = torch.cat(parts, dim=1)
         mean, err = rp.yield_stats(phi.reshape(-1, M))
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t0) / args.steps
     prof = None
-    if name in ("large", "paper"):   # one extra profiled call (tiled kernels) for the term-kernel bandwidth
+    if name in ("large", "paper") and not args.no_profile_call:
+        # one extra profiled call (tiled kernels) for the term-kernel bandwidth
         rp.propagate(systems, B, cat, M, precision=args.precision, profile=True)
         p = rp.profile_last()
         prof = {"term_ms": p["term_ms"], "quad_ms": p["quad_ms"], "total_ms": p["total_ms"],
@@ -229,6 +239,7 @@ def other_workload(args):
            "config": {"workload": w.name, "systems": len(systems), "fields": int(B.shape[1]), "samples": M,
                       "Z_min": min(Zs), "Z_max": max(Zs)},
            "phi_mean_first_system": [round(float(x), 6) for x in mean[:B.shape[1]].cpu().numpy()],
+           "phi_err_first_system": [round(float(x), 6) for x in err[:B.shape[1]].cpu().numpy()],
            "fields_first_system": [round(float(x), 4) for x in B[0]], "profile": prof}
     print(json.dumps(rec), flush=True)
 
@@ -347,6 +358,10 @@ def main():
     ap.add_argument("--workload", default="sweep",
                     choices=["sweep", "tiny", "batched", "large", "paper", "trace", "sampling", "arnoldi"])
     ap.add_argument("--trace-n", type=int, default=10, help="trace workload: nuclei of the batched system used")
+    ap.add_argument("--field-group", type=int, default=0,
+                    help="large/paper workloads: fields per call, with a progress line after each (0: all)")
+    ap.add_argument("--no-profile-call", action="store_true",
+                    help="large/paper workloads: skip the extra profiled call")
     ap.add_argument("--stride", type=int, default=8, help="batched workload: take every stride-th system")
     ap.add_argument("--max-n", type=int, default=12, help="batched workload: only systems with at most this many nuclei")
     ap.add_argument("--cv", action="store_true",
