@@ -339,6 +339,36 @@ def arnoldi_ablation(args):
                           "max_rel_diff": float(diff.max())}), flush=True)
 
 
+def histogram(args):
+    """Distribution of single-wavepacket yields of the Sec. IV model at three fields (the
+    paper's Fig. 4 workload: 1000 samples per field): mean, sigma (Eq. 23), quantiles and a
+    20-bin histogram per field; the paper bounds sigma by 1/2."""
+    import torch
+    from paper_1612_09517_amd import rp, workloads
+    torch.cuda.set_device(0)
+    w = workloads.paper_model()
+    s = w.systems[0]
+    M = args.samples_per_step
+    t0 = time.perf_counter()
+    out = []
+    for B in (0.0, 3.5, 10.0):
+        parts = []
+        for m0 in range(0, M, 250):
+            m = min(250, M - m0)
+            ang = rp.sample(s, w.seed, m, first=m0)
+            parts.append(rp.propagate(s, np.array([[B]]), ang, m, precision=args.precision)[0, 0].cpu().numpy())
+            print(json.dumps({"progress": f"B={B} samples {m0 + m}/{M}", "t_s": round(time.perf_counter() - t0, 1)}),
+                  flush=True)
+        phi = np.concatenate(parts)
+        h, edges = np.histogram(phi, bins=20, range=(0.0, 1.0))
+        out.append({"B_mT": B, "mean": float(phi.mean()), "sigma": float(phi.std(ddof=1)),
+                    "eps": float(phi.std(ddof=1) / np.sqrt(M)), "min": float(phi.min()), "max": float(phi.max()),
+                    "quantiles_5_25_50_75_95": [float(q) for q in np.quantile(phi, [0.05, 0.25, 0.5, 0.75, 0.95])],
+                    "histogram_0_to_1_20_bins": h.tolist()})
+    print(json.dumps({"metric": "single-wavepacket yield distribution, Sec. IV model", "samples": M,
+                      "dtype": f"f{args.precision}", "wall_s": time.perf_counter() - t0, "fields": out}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -356,7 +386,8 @@ def main():
     ap.add_argument("--copy-probe", type=float, default=0.0,
                     help="only copy a buffer of this many GiB three times (calibrates HBM counters)")
     ap.add_argument("--workload", default="sweep",
-                    choices=["sweep", "tiny", "batched", "large", "paper", "trace", "sampling", "arnoldi"])
+                    choices=["sweep", "tiny", "batched", "large", "paper", "trace", "sampling", "arnoldi",
+                             "histogram"])
     ap.add_argument("--trace-n", type=int, default=10, help="trace workload: nuclei of the batched system used")
     ap.add_argument("--field-group", type=int, default=0,
                     help="large/paper workloads: fields per call, with a progress line after each (0: all)")
@@ -389,6 +420,9 @@ def main():
         return
     if args.workload == "arnoldi":
         arnoldi_ablation(args)
+        return
+    if args.workload == "histogram":
+        histogram(args)
         return
     if args.workload != "sweep":
         other_workload(args)
