@@ -14,6 +14,7 @@ cos theta = 2 u1 - 1 and phi = 2 pi u2.
 import math
 
 import numpy as np
+from scipy.linalg import hadamard
 
 _MASK = (1 << 64) - 1
 _M0, _M1 = 0xD2E7470EE14C6C93, 0xCA5A826395121157      # round multipliers
@@ -60,6 +61,41 @@ def flip(angles, mask):
     a[mask, 0] = -a[mask, 0]
     a[mask, 1] = np.mod(a[mask, 1] + math.pi, TWO_PI)
     return a
+
+
+def design_rows(N, mode):
+    """Sign-flip design for N nuclei as a [R][N] array of +-1 (row r, nucleus k).
+
+    mode 3, antithetic pairs: R = 2, rows (+1, ..., +1) and (-1, ..., -1).
+    mode 4, fold-over of the Sylvester-Hadamard matrix H of order n (n the smallest power of
+    two >= N, columns 0 .. N-1): rows H[r] for r < n and -H[r - n] for r >= n, R = 2n.  The
+    fold-over cancels every odd product of columns and the orthogonality of Hadamard columns
+    every product of two, so the rows form an orthogonal array of strength 3.
+    """
+    if mode == 3:
+        return np.array([[1] * N, [-1] * N], int)
+    n = 1
+    while n < N:
+        n *= 2
+    H = hadamard(n)[:, :N]
+    return np.concatenate([H, -H], axis=0)
+
+
+def sample_design(seed, first_sample, M, N, mode, stream=STREAM_EVAL):
+    """Directions of a sign-flip design (modes 3 and 4 of the sampler): global sample index
+    q = first_sample + s belongs to group g = q // R and row r = q % R of ``design_rows``; the
+    group draws one set of directions as ``sample_angles`` does for sample g, and row r takes
+    n_k -> -n_k wherever its sign is -1.  Every sample is marginally uniform on the spheres, so
+    the mean over a group is an unbiased estimate of the Eq. 18 trace, and the groups are
+    independent."""
+    D = design_rows(N, mode)
+    R = D.shape[0]
+    out = np.empty((M, N, 2), float)
+    for s in range(M):
+        q = first_sample + s
+        base = sample_angles(seed, q // R, 1, N, stream)[0]
+        out[s] = flip(base, D[q % R] < 0)
+    return out
 
 
 def sample_basis_digits(seed, first_sample, M, two_I, stream=STREAM_EVAL):

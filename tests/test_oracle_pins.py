@@ -242,6 +242,64 @@ def test_antithetic_average_equals_trace():
     assert abs(np.mean(vals) - fo.trace_yield()) < 1e-13
 
 
+@pytest.mark.parametrize("N", list(range(1, 21)))
+def test_design_rows_orthogonal_array(N):
+    """Definition of an orthogonal array of strength 3, checked by counting: for every three
+    nuclei (two, one when N is smaller) each sign pattern occurs in exactly R / 2^t rows.  The
+    antithetic pair has strength 1 only: every nucleus balanced, pairs never (N >= 2)."""
+    D = philox.design_rows(N, 4)
+    R = D.shape[0]
+    assert R >= 2 * N and R & (R - 1) == 0 and set(np.unique(D)) <= {-1, 1}
+    t = min(3, N)
+    for cols in itertools.combinations(range(N), t):
+        pats = {}
+        for row in D[:, cols]:
+            pats[tuple(row)] = pats.get(tuple(row), 0) + 1
+        assert len(pats) == 2 ** t and set(pats.values()) == {R // 2 ** t}
+    A = philox.design_rows(N, 3)
+    assert A.shape == (2, N) and np.all(A.sum(axis=0) == 0)
+    if N >= 2:
+        assert np.all(A[:, 0] * A[:, 1] == 1)
+
+
+def test_design_group_mean_equals_trace():
+    """phi_S is multilinear in the nuclear Bloch vectors for spin-1/2 nuclei (the sign-flip
+    argument), so averaging over a design that cancels every product of up to N sign flips
+    leaves the Eq. 14 trace: exact for the strength-3 design with N = 3, and for the
+    antithetic pair with N = 1.  The antithetic pair leaves the two-nucleus terms for N = 3."""
+    s = spin.DenseSystem((2, 1), [1, 1, 1], [0.8, -0.3, 0.5], J_mT=0.4, kS=2.0, kT=0.5)
+    fo = yields.FieldOracle(s, 1.2, 5.0)
+    tr = fo.trace_yield()
+    for g in range(2):
+        ang = philox.sample_design(13, 8 * g, 8, 3, 4)
+        assert abs(np.mean([fo.phi(coherent.initial_wavepacket(s, a)) for a in ang]) - tr) < 1e-13
+    pair = philox.sample_design(13, 0, 2, 3, 3)
+    assert abs(np.mean([fo.phi(coherent.initial_wavepacket(s, a)) for a in pair]) - tr) > 1e-4
+    s1 = spin.DenseSystem((1, 0), [1], [1.3], kS=1.0, kT=0.3)
+    f1 = yields.FieldOracle(s1, 0.5, 6.0)
+    for g in range(3):
+        pair = philox.sample_design(21, 2 * g, 2, 1, 3)
+        assert abs(np.mean([f1.phi(coherent.initial_wavepacket(s1, a)) for a in pair]) - f1.trace_yield()) < 1e-13
+
+
+def test_design_samples_flip_a_shared_draw():
+    """Rows of one group share the group's draw: cos(theta) changes sign and phi moves by pi
+    (mod 2 pi) exactly where the design has -1; a ragged start and end split groups as the
+    global sample index does."""
+    N, R = 5, 16
+    a = philox.sample_design(3, 0, 2 * R, N, 4)
+    D = philox.design_rows(N, 4)
+    for q in range(2 * R):
+        base = philox.sample_angles(3, q // R, 1, N)[0]
+        for k in range(N):
+            sg = D[q % R, k]
+            assert a[q, k, 0] == sg * base[k, 0]
+            want = base[k, 1] if sg > 0 else (base[k, 1] + math.pi) % (2 * math.pi)
+            assert a[q, k, 1] == want and 0.0 <= a[q, k, 1] < 2 * math.pi
+    b = philox.sample_design(3, 5, 20, N, 4)
+    assert np.array_equal(b, a[5:25])
+
+
 def test_basis_state_samples_are_eq14_terms():
     """theta in {0, pi} turns |Omega> into |m = +-1/2>; averaging over all corners gives Eq. 14."""
     s = spin.DenseSystem((2, 1), [1, 1, 1], [0.8, -0.3, 0.5], J_mT=0.0, kS=1.0, kT=0.25)
