@@ -71,18 +71,23 @@ def design_rows(N, mode):
     two >= N, columns 0 .. N-1): rows H[r] for r < n and -H[r - n] for r >= n, R = 2n.  The
     fold-over cancels every odd product of columns and the orthogonality of Hadamard columns
     every product of two, so the rows form an orthogonal array of strength 3.
+    mode 5, columns 1 .. N of the Sylvester-Hadamard matrix of order n (n the smallest power
+    of two > N), R = n: every column but the first is balanced and any two are orthogonal, an
+    orthogonal array of strength 2.
     """
     if mode == 3:
         return np.array([[1] * N, [-1] * N], int)
     n = 1
-    while n < N:
+    while n < (N + 1 if mode == 5 else N):
         n *= 2
+    if mode == 5:
+        return hadamard(n)[:, 1:N + 1]
     H = hadamard(n)[:, :N]
     return np.concatenate([H, -H], axis=0)
 
 
 def sample_design(seed, first_sample, M, N, mode, stream=STREAM_EVAL):
-    """Directions of a sign-flip design (modes 3 and 4 of the sampler): global sample index
+    """Directions of a sign-flip design (modes 3, 4 and 5 of the sampler): global sample index
     q = first_sample + s belongs to group g = q // R and row r = q % R of ``design_rows``; the
     group draws one set of directions as ``sample_angles`` does for sample g, and row r takes
     n_k -> -n_k wherever its sign is -1.  Every sample is marginally uniform on the spheres, so

@@ -260,13 +260,22 @@ def test_design_rows_orthogonal_array(N):
     assert A.shape == (2, N) and np.all(A.sum(axis=0) == 0)
     if N >= 2:
         assert np.all(A[:, 0] * A[:, 1] == 1)
+    S = philox.design_rows(N, 5)
+    R2 = S.shape[0]
+    assert R2 > N and R2 & (R2 - 1) == 0 and R2 < 2 * (N + 1)
+    for cols in itertools.combinations(range(N), min(2, N)):
+        pats = {}
+        for row in S[:, cols]:
+            pats[tuple(row)] = pats.get(tuple(row), 0) + 1
+        assert len(pats) == 2 ** len(cols) and set(pats.values()) == {R2 // 2 ** len(cols)}
 
 
 def test_design_group_mean_equals_trace():
     """phi_S is multilinear in the nuclear Bloch vectors for spin-1/2 nuclei (the sign-flip
     argument), so averaging over a design that cancels every product of up to N sign flips
-    leaves the Eq. 14 trace: exact for the strength-3 design with N = 3, and for the
-    antithetic pair with N = 1.  The antithetic pair leaves the two-nucleus terms for N = 3."""
+    leaves the Eq. 14 trace: exact for the strength-3 design with N = 3, the strength-2 design
+    with N = 2 and the antithetic pair with N = 1; the antithetic pair leaves the two-nucleus
+    terms for N = 3, the strength-2 design the three-nucleus term."""
     s = spin.DenseSystem((2, 1), [1, 1, 1], [0.8, -0.3, 0.5], J_mT=0.4, kS=2.0, kT=0.5)
     fo = yields.FieldOracle(s, 1.2, 5.0)
     tr = fo.trace_yield()
@@ -275,6 +284,15 @@ def test_design_group_mean_equals_trace():
         assert abs(np.mean([fo.phi(coherent.initial_wavepacket(s, a)) for a in ang]) - tr) < 1e-13
     pair = philox.sample_design(13, 0, 2, 3, 3)
     assert abs(np.mean([fo.phi(coherent.initial_wavepacket(s, a)) for a in pair]) - tr) > 1e-4
+    # strength 2 with three nuclei: columns 1, 2, 3 of order 4 multiply to the constant column,
+    # so the three-nucleus term survives; with two nuclei the design is exact
+    oa2 = philox.sample_design(13, 0, 4, 3, 5)
+    assert abs(np.mean([fo.phi(coherent.initial_wavepacket(s, a)) for a in oa2]) - tr) > 1e-6
+    s2 = spin.DenseSystem((1, 1), [1, 1], [0.7, -0.45], J_mT=-0.2, kS=0.9, kT=1.7)
+    f2 = yields.FieldOracle(s2, 2.2, 4.0)
+    for g in range(2):
+        ang = philox.sample_design(17, 4 * g, 4, 2, 5)
+        assert abs(np.mean([f2.phi(coherent.initial_wavepacket(s2, a)) for a in ang]) - f2.trace_yield()) < 1e-13
     s1 = spin.DenseSystem((1, 0), [1], [1.3], kS=1.0, kT=0.3)
     f1 = yields.FieldOracle(s1, 0.5, 6.0)
     for g in range(3):
