@@ -276,28 +276,135 @@ def trace_vs_mc(args):
                       "max_abs_dev_over_eps": float(z.max()), "dtype": f"f{args.precision}"}), flush=True)
 
 
+def design_headline(args):
+    """Sweep wall time to eps <= 1e-3 at every field with coherent states in a sign-flip design
+    (rp_sample mode 5 by default: strength-2 orthogonal array, 16 samples per group for N = 14)
+    in complex FP32, measured end to end: groups are added to the fields whose standard error
+    (over group means) is above eps until none is, starting from --design-groups groups.
+    Plain FP64 and plain FP32 Monte Carlo wall times follow from measured rates and the
+    per-sample deviation of a plain pilot, as M_needed * fields / rate.  Same workload as --cv."""
+    import torch
+    from paper_1612_09517_amd import rp, workloads
+    w = workloads.cv_c5()
+    s = w.systems[0]
+    B = w.fields_mT[0]
+    nB = len(B)
+    torch.cuda.set_device(0)
+    sync = torch.cuda.synchronize
+    eps = 1e-3
+    mode = args.design_mode
+    R = rp.design_size(s.N, mode)
+    t00 = time.perf_counter()
+
+    def say(msg):
+        print(json.dumps({"progress": msg, "t_s": round(time.perf_counter() - t00, 1)}), flush=True)
+
+    # group means per field, grown until every field's error is below eps
+    sync()
+    t0 = time.perf_counter()
+    gm = [None] * nB                     # per field: CUDA tensor of its group means
+    mean_d, err_d = np.zeros(nB), np.full(nB, np.inf)
+    need = np.full(nB, args.design_groups)
+    done = np.zeros(nB, int)
+    props = 0
+    rounds = 0
+    while True:
+        todo = np.nonzero(need > done)[0]
+        if todo.size == 0:
+            break
+        G = int(np.max(need[todo] - done[todo]))
+        first = int(done[todo].max()) * R   # fresh groups for every field in this round
+        a = rp.sample(s, w.seed, G * R, first=first, basis_mode=mode)
+        g = rp.group_mean(rp.propagate(s, B[todo][None, :], a, G * R, precision=32)[0], R)
+        props += G * R * todo.size
+        for j, f in enumerate(todo):
+            gm[f] = g[j] if gm[f] is None else torch.cat([gm[f], g[j]])
+            done[f] = gm[f].numel()
+            m, e = rp.yield_stats(gm[f][None, :])
+            mean_d[f], err_d[f] = float(m[0]), float(e[0])
+        need = np.where(err_d > eps, np.ceil(done * (err_d / eps) ** 2 * 1.05).astype(int), done)
+        rounds += 1
+        say(f"round {rounds}: {props} propagations, max error {err_d.max():.2e}")
+    sync()
+    wall_design = time.perf_counter() - t0
+    # plain pilot (FP32) and the FP64 rate
+    Me = args.cv_eval
+    t0 = time.perf_counter()
+    a_ev = rp.sample(s, w.seed + 1, Me)
+    phi_ev = rp.propagate(s, B[None, :], a_ev, Me, precision=32)[0]
+    sync()
+    rate32 = Me * nB / (time.perf_counter() - t0)
+    m_pl, e_pl = (x.cpu().numpy() for x in rp.yield_stats(phi_ev))
+    say(f"plain pilot done, {rate32:.1f} propagations/s")
+    M64 = max(4, Me // 8)
+    t0 = time.perf_counter()
+    rp.propagate(s, B[None, :], rp.sample(s, w.seed + 2, M64), M64, precision=64)
+    sync()
+    rate64 = M64 * nB / (time.perf_counter() - t0)
+    sig_pl = e_pl * np.sqrt(Me)
+    M_pl = float(np.ceil(np.max((sig_pl / eps) ** 2)))
+    wall64 = M_pl * nB / rate64
+    wall32 = M_pl * nB / rate32
+    # variance of the mean from n samples: plain sigma^2 / n, design err^2 G R / n
+    vr = sig_pl ** 2 / (err_d ** 2 * done * R)
+    rec = {"metric": "sweep wall time at sigma(Phi_S)<=1e-3: FP32 + sign-flip design vs plain FP64 MC",
+           "value": wall_design, "unit": "s", "higher_is_better": False, "n_gpus": 1, "data": "synthetic",
+           "dtype": "f32", "config": {"workload": w.name + ": N=14 spin-1/2, Z=16384, 32 fields 0..5 mT",
+                                      "design_mode": mode, "samples_per_group": R,
+                                      "initial_groups": args.design_groups, "plain_pilot_samples": Me},
+           "plain_fp64_wall_s": wall64, "plain_fp32_wall_s": wall32, "speedup_vs_fp64": wall64 / wall_design,
+           "speedup_vs_fp32": wall32 / wall_design,
+           "rate_fp32_props_s": rate32, "rate_fp64_props_s": rate64, "design_propagations": props,
+           "design_rounds": rounds, "groups_min": int(done.min()), "groups_max": int(done.max()),
+           "samples_needed": {"plain": M_pl, "design_max": int(done.max()) * R},
+           "design_err_max": float(err_d.max()), "sigma_plain_max": float(sig_pl.max()),
+           "variance_reduction_at_equal_samples": {"min": float(vr.min()), "median": float(np.median(vr)),
+                                                   "max": float(vr.max())},
+           "design_minus_plain_over_err": float(np.max(np.abs(mean_d - m_pl) / np.sqrt(err_d ** 2 + e_pl ** 2)))}
+    print(json.dumps(rec), flush=True)
+
+
 def sampling_variance(args):
-    """Coherent states (Eq. 15) against random J_z eigenstates (Sec. V, last paragraph) as Monte
-    Carlo samples: per-sample standard deviation of the yield at equal cost, on the sweep system."""
+    """Monte Carlo samplers at equal cost on the sweep system: coherent states (Eq. 15), random
+    J_z eigenstates (Sec. V, last paragraph), and coherent states in sign-flip designs
+    (antithetic pairs, orthogonal arrays of strength 3 and 2: the uniform measure of Eq. 17 is
+    invariant under n -> -n).  Reports the per-sample standard deviation and, for every
+    sampler, the variance of its estimate of the mean with M propagations (design groups as
+    the independent units)."""
     import torch
     from paper_1612_09517_amd import rp, workloads
     torch.cuda.set_device(0)
     w = workloads.sweep_c2()
     s = w.systems[0]
     B = np.array([[0.0, 2.5, 10.0]])
-    M = args.samples_per_step
-    coh = rp.propagate(s, B, rp.sample(s, w.seed, M), M, precision=args.precision)[0]
-    jz = rp.propagate(s, B, rp.sample(s, w.seed, M, basis_mode=1), M, init_mode=1, precision=args.precision)[0]
-    mc, ec = rp.yield_stats(coh)
-    mj, ej = rp.yield_stats(jz)
-    sc = (ec * np.sqrt(M)).cpu().numpy()
-    sj = (ej * np.sqrt(M)).cpu().numpy()
-    print(json.dumps({"metric": "per-sample yield std, coherent vs J_z eigenstates", "system": s.name,
-                      "fields_mT": B[0].tolist(), "M": M, "sigma_coherent": sc.tolist(), "sigma_jz": sj.tolist(),
-                      "variance_ratio_jz_over_coherent": (sj ** 2 / sc ** 2).tolist(),
-                      "mean_coherent": mc.cpu().numpy().tolist(), "mean_jz": mj.cpu().numpy().tolist(),
-                      "mean_diff_over_eps": (torch.abs(mc - mj) / torch.sqrt(ec ** 2 + ej ** 2)).cpu().numpy().tolist(),
-                      "dtype": f"f{args.precision}"}), flush=True)
+    R4 = rp.design_size(s.N, 4)
+    M = -(-args.samples_per_step // R4) * R4          # whole design groups
+    out = {}
+    for name, mode in (("coherent", 0), ("jz", 1), ("antithetic", 3), ("oa3", 4), ("oa2", 5)):
+        t0 = time.time()
+        ang = rp.sample(s, w.seed, M, basis_mode=mode)
+        phi = rp.propagate(s, B, ang, M, init_mode=1 if mode == 1 else 0, precision=args.precision)[0]
+        R = rp.design_size(s.N, mode)
+        units = rp.group_mean(phi, R) if R > 1 else phi
+        mean, err = rp.yield_stats(units)
+        _, err1 = rp.yield_stats(phi)
+        torch.cuda.synchronize()
+        out[name] = {"mean": mean.cpu().numpy(), "est_var": (err ** 2).cpu().numpy(),
+                     "per_sample_sigma": (err1 * np.sqrt(M)).cpu().numpy(), "group": R,
+                     "units": M // R}
+        print(f"sampler {name}: {M} propagations x {B.shape[1]} fields in {time.time() - t0:.1f} s",
+              file=sys.stderr, flush=True)
+    c = out["coherent"]
+    rec = {"metric": "Monte Carlo samplers at equal cost (variance of the mean estimate)", "system": s.name,
+           "fields_mT": B[0].tolist(), "M": M, "dtype": f"f{args.precision}"}
+    for name, v in out.items():
+        rec[name] = {"group": v["group"], "independent_units": v["units"],
+                     "per_sample_sigma": v["per_sample_sigma"].tolist(),
+                     "mean": v["mean"].tolist(), "stderr": np.sqrt(v["est_var"]).tolist(),
+                     "variance_reduction_vs_coherent": (c["est_var"] / v["est_var"]).tolist(),
+                     "mean_diff_over_eps": (np.abs(v["mean"] - c["mean"]) /
+                                            np.sqrt(v["est_var"] + c["est_var"])).tolist()}
+    print(json.dumps(rec), flush=True)
 
 
 def arnoldi_ablation(args):
@@ -402,12 +509,19 @@ def main():
     ap.add_argument("--cv-no-augment", action="store_true", help="train without the field-axis rotations")
     ap.add_argument("--cv-quad", type=int, default=65536, help="samples for the mean of the network")
     ap.add_argument("--cv-eval", type=int, default=128, help="evaluation samples (pilot)")
+    ap.add_argument("--design", action="store_true",
+                    help="sweep to eps <= 1e-3 with sign-flip design sampling (FP32) against plain FP64")
+    ap.add_argument("--design-mode", type=int, default=5, choices=[3, 4, 5], help="rp_sample design mode")
+    ap.add_argument("--design-groups", type=int, default=8, help="design groups per field to start with")
     ap.add_argument("--summarize", default="",
                     help="print a per-kernel summary of a rocprofv3 CSV directory and exit")
     args = ap.parse_args()
     if args.summarize:
         for k, v in sorted(summarize(args.summarize).items(), key=lambda kv: -kv[1].get("pct", 0)):
             print(json.dumps({"kernel": k, **v}))
+        return
+    if args.design:
+        design_headline(args)
         return
     if args.cv:
         cv_headline(args)

@@ -124,11 +124,38 @@ typedef struct rp_opts {
  *                1: random basis states, digit n = floor(u1 (2I+1)) (Sec. V, last
  *                   paragraph: sampling of J_z eigenstates);
  *                2: deterministic enumeration, sample s -> digits of s in the mixed
- *                   radix of the nuclei (first nucleus fastest), for the Eq. 14 sum.
+ *                   radix of the nuclei (first nucleus fastest), for the Eq. 14 sum;
+ *                3, 4, 5: coherent-state directions in sign-flip designs, a variance
+ *                   reduction of the Eq. 18 mean (the measure of Eq. 17 is invariant under
+ *                   n -> -n).  The global sample index q = first_sample + s lies in group
+ *                   q / R, row q % R, with R = rp_design_size(N1+N2, basis_mode).  The
+ *                   group draws directions as mode 0 does for sample index q / R; row r
+ *                   maps n_k -> -n_k (cos theta -> -cos theta, phi -> phi + pi, reduced
+ *                   below 2 pi) where its sign is -1.
+ *                   Mode 3: antithetic pair, R = 2, row 1 flips every nucleus.
+ *                   Mode 4: fold-over of the Sylvester-Hadamard matrix of order n (the
+ *                   smallest power of two >= N1+N2), R = 2n; sign of nucleus k in row r is
+ *                   (-1)^popcount((r mod n) & k), negated for r >= n: an orthogonal array
+ *                   of strength 3.
+ *                   Mode 5: columns 1.. of the Sylvester-Hadamard matrix of order R, the
+ *                   smallest power of two > N1+N2; sign (-1)^popcount(r & (k+1)): an
+ *                   orthogonal array of strength 2.
+ *                   Each sample is marginally uniform, so each group's mean is unbiased and
+ *                   the groups are independent: take the error from group means
+ *                   (rp_group_mean, then rp_yield), with first_sample and M multiples of
+ *                   R.  Use init_mode 0 in rp_propagate.
  *   angles       device, [M][N1+N2][2] doubles, written.
  */
 int rp_sample(const rp_system *s, uint64_t seed, uint32_t stream_id, uint64_t first_sample,
               int64_t M, int32_t basis_mode, double *angles, void *hip_stream);
+
+/*
+ * rp_design_size -- samples per group R of rp_sample's basis_mode for n_nuclei nuclei: 1 for
+ * modes 0-2, 2 for mode 3, 2n for mode 4 (n the smallest power of two >= n_nuclei), the
+ * smallest power of two > n_nuclei for mode 5.  Host only; returns RP_EINVAL (negative) for
+ * a mode outside 0..5 or n_nuclei outside 0..RP_MAX_NUCLEI.
+ */
+int64_t rp_design_size(int32_t n_nuclei, int32_t basis_mode);
 
 /*
  * rp_propagate -- single-wavepacket singlet yields phi_S (Eq. 22 on [0, T]) for
@@ -175,6 +202,19 @@ int rp_propagate(const rp_system *sys, int32_t n_sys, const double *B_mT, int32_
 int rp_yield(const double *phi, int32_t nB, int64_t M, const double *cv_g, const double *cv_mu,
              const double *cv_beta, const double *cv_mu_err, double *mean, double *stderr_,
              void *hip_stream);
+
+/*
+ * rp_group_mean -- means of consecutive groups of samples: out[b][j] = (1/group)
+ * sum_{i < group} phi[b][j group + i], summed in order in FP64.  For the sign-flip designs of
+ * rp_sample (modes 3-5) each group mean is one independent unbiased estimate of the Eq. 18
+ * trace; rp_yield over the M / group means gives the design estimate and its standard error
+ * (Eq. 23 with the groups as samples).
+ *
+ *   phi    device, [nB][M] doubles
+ *   group  samples per group, >= 1 and dividing M (else RP_EINVAL)
+ *   out    device, [nB][M / group] doubles, written
+ */
+int rp_group_mean(const double *phi, int32_t nB, int64_t M, int64_t group, double *out, void *hip_stream);
 
 /*
  * Learned control variate (for the Monte Carlo mean of Eq. 18).  A network g(Omega, B)

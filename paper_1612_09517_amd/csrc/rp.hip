@@ -77,6 +77,7 @@ struct SampleArgs {
   uint32_t stream;
   int32_t d[RP_MAX_NUCLEI];
   int64_t radix[RP_MAX_NUCLEI];
+  uint64_t rows;   // modes 3 and 4: rows of the sign-flip design (samples per group)
 };
 
 __device__ __forceinline__ void philox4x64_10(uint64_t c[4], uint64_t k0, uint64_t k1) {
@@ -102,14 +103,39 @@ __global__ __launch_bounds__(256) void k_sample(SampleArgs a) {
   if (i >= a.M * a.N) return;
   const int64_t s = i / a.N;
   const int k = (int)(i - s * a.N);
-  uint64_t c[4] = {a.first + (uint64_t)s, (uint64_t)k, 0ull, 0ull};
+  // Sign-flip designs draw one set of directions per group of `rows` consecutive samples.
+  const uint64_t q = a.first + (uint64_t)s;
+  const bool design = a.mode >= 3;
+  uint64_t c[4] = {design ? q / a.rows : q, (uint64_t)k, 0ull, 0ull};
   philox4x64_10(c, a.seed, (uint64_t)a.stream);
   const double u1 = ((double)(c[0] >> 12) + 0.5) * 0x1p-52;
   const double u2 = ((double)(c[1] >> 12) + 0.5) * 0x1p-52;
   double v0, v1 = 0.0;
-  if (a.mode == 0) {
+  if (a.mode == 0 || design) {
     v0 = 2.0 * u1 - 1.0;
     v1 = 6.283185307179586 * u2;
+    if (design) {
+      // Row r of the design: antithetic pair (mode 3); the fold-over of the Sylvester-Hadamard
+      // matrix of order n = rows / 2, entry (-1)^popcount(r & k), negated for r >= n (mode 4);
+      // column k + 1 of the Sylvester-Hadamard matrix of order rows (mode 5).  A -1 maps n_k
+      // to -n_k: cos theta -> -cos theta, phi -> phi + pi (mod 2 pi).
+      const uint64_t r = q % a.rows;
+      bool neg;
+      if (a.mode == 3) {
+        neg = r == 1;
+      } else if (a.mode == 4) {
+        const uint64_t n = a.rows >> 1;
+        const uint64_t rr = r < n ? r : r - n;
+        neg = ((__popcll(rr & (uint64_t)k) & 1) != 0) != (r >= n);
+      } else {
+        neg = (__popcll(r & (uint64_t)(k + 1)) & 1) != 0;
+      }
+      if (neg) {
+        v0 = -v0;
+        v1 = v1 + 3.141592653589793;
+        if (v1 >= 6.283185307179586) v1 -= 6.283185307179586;
+      }
+    }
   } else if (a.mode == 1) {
     int dg = (int)(u1 * (double)a.d[k]);
     v0 = (double)(dg < a.d[k] ? dg : a.d[k] - 1);
@@ -1670,12 +1696,26 @@ extern "C" int rp_plan_field(const rp_system *s, double B_mT, const rp_opts *opt
   return RP_OK;
 }
 
+extern "C" int64_t rp_design_size(int32_t n_nuclei, int32_t basis_mode) {
+  if (n_nuclei < 0 || n_nuclei > RP_MAX_NUCLEI || basis_mode < 0 || basis_mode > 5)
+    return fail(RP_EINVAL, "rp_design_size: n_nuclei or basis_mode out of range");
+  if (basis_mode < 3) return 1;
+  if (basis_mode == 3) return 2;
+  int64_t n = 1;
+  if (basis_mode == 5) {
+    while (n <= n_nuclei) n *= 2;
+    return n;
+  }
+  while (n < n_nuclei) n *= 2;
+  return 2 * n;
+}
+
 extern "C" int rp_sample(const rp_system *s, uint64_t seed, uint32_t stream_id, uint64_t first_sample, int64_t M,
                          int32_t basis_mode, double *angles, void *hip_stream) {
   int rc = validate_system(s);
   if (rc) return rc;
   if (M < 0) return fail(RP_EINVAL, "M < 0");
-  if (basis_mode < 0 || basis_mode > 2) return fail(RP_EINVAL, "basis_mode must be 0, 1 or 2");
+  if (basis_mode < 0 || basis_mode > 5) return fail(RP_EINVAL, "basis_mode must be 0 .. 5");
   const int N = s->n_nuc[0] + s->n_nuc[1];
   if (M == 0 || N == 0) return RP_OK;
   if (!angles) return fail(RP_EINVAL, "null angles");
@@ -1695,6 +1735,7 @@ extern "C" int rp_sample(const rp_system *s, uint64_t seed, uint32_t stream_id, 
     a.radix[k] = rad;
     rad *= a.d[k];
   }
+  a.rows = basis_mode >= 3 ? (uint64_t)rp_design_size(N, basis_mode) : 1;
   hipLaunchKernelGGL(k_sample, dim3(grid1(M * N)), dim3(256), 0, (hipStream_t)hip_stream, a);
   HIPCHK(hipGetLastError());
   return RP_OK;
@@ -2337,6 +2378,28 @@ extern "C" int rp_combine(const double *mean_a, const double *err_a, const doubl
   if (!mean_a || !err_a || !mean_b || !err_b || !mean || !err) return fail(RP_EINVAL, "null pointer");
   hipLaunchKernelGGL(k_combine, dim3(grid1(nB)), dim3(256), 0, (hipStream_t)hip_stream, mean_a, err_a, mean_b, err_b,
                      nB, mean, err);
+  HIPCHK(hipGetLastError());
+  return RP_OK;
+}
+
+__global__ __launch_bounds__(256) void k_group_mean(const double *phi, int64_t n_out, int64_t group, double *out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n_out) return;
+  const double *p = phi + i * group;
+  double t = 0.0;
+  for (int64_t j = 0; j < group; ++j) t += p[j];
+  out[i] = t / (double)group;
+}
+
+extern "C" int rp_group_mean(const double *phi, int32_t nB, int64_t M, int64_t group, double *out,
+                             void *hip_stream) {
+  if (nB < 0 || M < 0) return fail(RP_EINVAL, "negative count");
+  if (group < 1 || M % group != 0) return fail(RP_EINVAL, "group must be >= 1 and divide M");
+  if (nB == 0 || M == 0) return RP_OK;
+  if (!phi || !out) return fail(RP_EINVAL, "null pointer");
+  const int64_t n_out = (int64_t)nB * (M / group);
+  hipLaunchKernelGGL(k_group_mean, dim3(grid1(n_out)), dim3(256), 0, (hipStream_t)hip_stream, phi, n_out, group,
+                     out);
   HIPCHK(hipGetLastError());
   return RP_OK;
 }

@@ -39,7 +39,8 @@ _lib = None
 
 EXPORTS = ["rp_sample", "rp_propagate", "rp_yield", "rp_strerror", "rp_last_error", "rp_bessel_j",
            "rp_plan_field", "rp_profile_last", "rp_mlp_param_count", "rp_mlp_workspace_floats",
-           "rp_mlp_features", "rp_mlp_forward", "rp_mlp_train_step", "rp_cv_beta", "rp_combine"]
+           "rp_mlp_features", "rp_mlp_forward", "rp_mlp_train_step", "rp_cv_beta", "rp_combine",
+           "rp_design_size", "rp_group_mean"]
 RP_FLAG_PROFILE = 1
 RP_FLAG_TILED = 2
 RP_FLAG_XCD_LOCAL = 4
@@ -69,6 +70,9 @@ def lib():
         L.rp_mlp_features.argtypes = [vp, i64, i32, vp, i32, i32, i32, u64, vp, vp]
         L.rp_cv_beta.argtypes = [vp, vp, i32, i64, vp, vp]
         L.rp_combine.argtypes = [vp, vp, vp, vp, i32, vp, vp, vp]
+        L.rp_design_size.argtypes = [i32, i32]
+        L.rp_design_size.restype = i64
+        L.rp_group_mean.argtypes = [vp, i32, i64, i64, vp, vp]
         L.rp_mlp_forward.argtypes = [i32, i32, i32, vp, vp, i64, vp, vp, vp]
         L.rp_mlp_train_step.argtypes = [i32, i32, i32, vp, vp, vp, i64, vp, vp, i64, ctypes.c_float, vp, vp,
                                         vp, vp]
@@ -79,7 +83,8 @@ def lib():
         L.rp_plan_field.argtypes = [sp, ctypes.c_double, op, dp, dp, dp]
         L.rp_profile_last.argtypes = [dp, i32]
         for f in ("rp_sample", "rp_propagate", "rp_yield", "rp_bessel_j", "rp_plan_field", "rp_profile_last",
-                  "rp_mlp_features", "rp_mlp_forward", "rp_mlp_train_step", "rp_cv_beta", "rp_combine"):
+                  "rp_mlp_features", "rp_mlp_forward", "rp_mlp_train_step", "rp_cv_beta", "rp_combine",
+                  "rp_group_mean"):
             getattr(L, f).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -127,8 +132,17 @@ def _dev_ptr(t, dtype):
 
 
 # ----------------------------------------------------------------------------- device entry points
+def design_size(n_nuclei, basis_mode):
+    """rp_design_size: samples per group of a sampler mode (1 for modes 0-2)."""
+    r = lib().rp_design_size(n_nuclei, basis_mode)
+    if r < 0:
+        _check(int(r))
+    return int(r)
+
+
 def sample(system: SpinSystem, seed, M, first=0, stream_id=0, basis_mode=0, out=None):
-    """rp_sample: [M][N][2] float64 CUDA tensor of directions (or basis digits)."""
+    """rp_sample: [M][N][2] float64 CUDA tensor of directions (or basis digits); modes 3 and 4
+    are the sign-flip designs (groups of design_size(N, mode) samples)."""
     import torch
     cs = _CSystem(system)
     if out is None:
@@ -180,6 +194,17 @@ def combine(mean_a, err_a, mean_b, err_b):
                             _dev_ptr(mean_b.contiguous(), torch.float64), _dev_ptr(err_b.contiguous(), torch.float64),
                             nB, _dev_ptr(mean, torch.float64), _dev_ptr(err, torch.float64), _stream(torch)))
     return mean, err
+
+
+def group_mean(phi, group):
+    """rp_group_mean: means of consecutive groups of ``group`` samples of phi [..][M] (CUDA float64)."""
+    import torch
+    phi = phi.reshape(-1, phi.shape[-1]).contiguous()
+    nB, M = phi.shape
+    out = torch.empty((nB, M // max(group, 1)), dtype=torch.float64, device="cuda")
+    _check(lib().rp_group_mean(_dev_ptr(phi, torch.float64), nB, M, group, _dev_ptr(out, torch.float64),
+                               _stream(torch)))
+    return out
 
 
 def yield_stats(phi, cv_g=None, cv_mu=None, cv_beta=None, cv_mu_err=None):

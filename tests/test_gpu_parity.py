@@ -50,6 +50,49 @@ def test_sampler_bit_exact(mode):
     assert np.array_equal(got, want)
 
 
+@pytest.mark.parametrize("mode", [3, 4, 5])
+def test_design_sampler_bit_exact(mode):
+    """Sign-flip designs: groups of rp_design_size samples share one draw; a ragged first
+    sample and count; five nuclei use Hadamard columns 0..4 of order 8 (16 rows) or columns
+    1..5 of order 8 (8 rows)."""
+    s = SpinSystem(3, 2, [1, 2, 1, 4, 1], [0.1] * 5)
+    _say("design sampler mode", mode)
+    R = rp.design_size(s.N, mode)
+    assert R == {3: 2, 4: 16, 5: 8}[mode]
+    got = rp.sample(s, seed=99, M=45, first=7, stream_id=1, basis_mode=mode).cpu().numpy()
+    want = philox.sample_design(99, 7, 45, s.N, mode, stream=1)
+    assert np.array_equal(got, want)
+
+
+def test_design_group_means_recover_trace():
+    """Three spin-1/2 nuclei: every group of the strength-3 design (8 samples) averages to the
+    Eq. 14 trace exactly (phi_S multilinear in the Bloch vectors), so the design estimate
+    has zero spread; rp_group_mean against a plain mean; the antithetic pair keeps spread;
+    two nuclei in the strength-2 design (4 samples per group) also give the trace."""
+    s = SpinSystem(2, 1, [1, 1, 1], [0.8, -0.3, 0.5], J_mT=0.4, kS=2.0, kT=0.5, T_us=5.0)
+    B = np.array([[1.2, 3.0]])
+    _say("design group means")
+    R = rp.design_size(s.N, 4)
+    ang = rp.sample(s, 13, 4 * R, basis_mode=4)
+    phi = rp.propagate(s, B, ang, 4 * R, precision=64)[0]
+    gm = rp.group_mean(phi, R)
+    ref = phi.cpu().numpy().reshape(2, 4, R).mean(axis=2)
+    assert gm.shape == (2, 4) and np.max(np.abs(gm.cpu().numpy() - ref)) < 1e-15
+    mean, err = rp.yield_stats(gm)
+    for b, Bv in enumerate(B[0]):
+        tr = gc.oracle_trace(s, Bv)
+        assert np.max(np.abs(gm.cpu().numpy()[b] - tr)) < 1e-10
+        assert abs(mean.cpu().numpy()[b] - tr) < 1e-10 and err.cpu().numpy()[b] < 1e-10
+    pair = rp.propagate(s, B, rp.sample(s, 13, 8, basis_mode=3), 8, precision=64)[0]
+    _, perr = rp.yield_stats(rp.group_mean(pair, 2))
+    assert np.all(perr.cpu().numpy() > 1e-6)
+    s2 = SpinSystem(1, 1, [1, 1], [0.7, -0.45], J_mT=-0.2, kS=0.9, kT=1.7, T_us=4.0)
+    R2 = rp.design_size(s2.N, 5)
+    gm2 = rp.group_mean(rp.propagate(s2, B, rp.sample(s2, 17, 3 * R2, basis_mode=5), 3 * R2, precision=64)[0], R2)
+    for b, Bv in enumerate(B[0]):
+        assert np.max(np.abs(gm2.cpu().numpy()[b] - gc.oracle_trace(s2, Bv))) < 1e-10
+
+
 # --------------------------------------------------------------------------- tiny workload (Z = 8)
 @pytest.mark.parametrize("tiled", [False, True])
 @pytest.mark.parametrize("prec", [64, 32])

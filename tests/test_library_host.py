@@ -132,6 +132,11 @@ def test_argument_validation_without_device():
     assert L.rp_propagate(ctypes.byref(cs.c), 1, dp, 2, fake, 4, ctypes.byref(o), fake, None, None) == rp.RP_EINVAL
     assert L.rp_sample(ctypes.byref(cs.c), 1, 0, 0, -1, 0, fake, None) == rp.RP_EINVAL
     assert L.rp_sample(ctypes.byref(cs.c), 1, 0, 0, 4, 7, fake, None) == rp.RP_EINVAL
+    assert L.rp_sample(ctypes.byref(cs.c), 1, 0, 0, 4, 6, fake, None) == rp.RP_EINVAL
+    assert L.rp_group_mean(fake, 3, 10, 4, fake, None) == rp.RP_EINVAL       # 4 does not divide 10
+    assert L.rp_group_mean(fake, 3, 10, 0, fake, None) == rp.RP_EINVAL
+    assert L.rp_group_mean(None, 3, 10, 5, fake, None) == rp.RP_EINVAL
+    assert L.rp_group_mean(fake, 0, 10, 5, fake, None) == rp.RP_OK           # nothing to do
     big = rp._CSystem(SpinSystem(1, 0, [5], [0.1]))
     assert L.rp_sample(ctypes.byref(big.c), 1, 0, 0, 4, 0, fake, None) == rp.RP_EINVAL
     assert L.rp_yield(None, 3, 4, None, None, None, None, fake, fake, None) == rp.RP_EINVAL
@@ -154,3 +159,18 @@ def test_autotune_cache_hit_needs_no_probe(tmp_path):
     cache.write_text(json.dumps({key: {"best": {"rdt": 120.0, "xcd": "spread"}, "probes": []}}))
     assert autotune.tune(s, B, precision=32, cache=str(cache)) == {"rdt": 120.0, "xcd": "spread"}
     assert autotune._key(s, 64, r_max) != key
+
+
+def test_design_size_matches_oracle_design():
+    """Samples per group of the sign-flip designs against the oracle's design matrices."""
+    from oracle import philox
+    for N in range(0, 41):
+        for mode in (0, 1, 2):
+            assert rp.design_size(N, mode) == 1
+        for mode in (3, 4, 5):
+            if N:
+                assert rp.design_size(N, mode) == philox.design_rows(N, mode).shape[0]
+    assert rp.lib().rp_design_size(3, 6) == rp.RP_EINVAL
+    assert rp.lib().rp_design_size(-1, 4) == rp.RP_EINVAL
+    with pytest.raises(rp.RpError):
+        rp.design_size(3, 9)
