@@ -65,7 +65,7 @@ def term_kernel_digest():
 def measured_traffic(precision, terms_per_step, elements_per_launch):
     """HBM bytes per term launch from the committed counter summary, or None when the
     term kernel's source has changed since the counters were taken (or for FP64, not measured)."""
-    f = os.path.join(ROOT, "profiles", "k_cheb_tile_c2_traffic.json")
+    f = os.path.join(ROOT, "profiles", "k_cheb_pair_c2_traffic.json")
     if precision != 32 or not os.path.exists(f):
         return None
     doc = json.load(open(f))
@@ -374,13 +374,19 @@ def sampling_variance(args):
     import torch
     from paper_1612_09517_amd import rp, workloads
     torch.cuda.set_device(0)
-    w = workloads.sweep_c2()
+    if args.sampling_system == "paper":
+        w = workloads.paper_model()
+        B = np.array([[1.0, 3.5]])
+    else:
+        w = workloads.sweep_c2()
+        B = np.array([[0.0, 2.5, 10.0]])
     s = w.systems[0]
-    B = np.array([[0.0, 2.5, 10.0]])
-    R4 = rp.design_size(s.N, 4)
-    M = -(-args.samples_per_step // R4) * R4          # whole design groups
+    modes = {"coherent": 0, "jz": 1, "antithetic": 3, "oa3": 4, "oa2": 5}
+    chosen = [(n, modes[n]) for n in args.samplers.split(",")]
+    Rmax = max(rp.design_size(s.N, m) for _, m in chosen)
+    M = -(-args.samples_per_step // Rmax) * Rmax      # whole design groups
     out = {}
-    for name, mode in (("coherent", 0), ("jz", 1), ("antithetic", 3), ("oa3", 4), ("oa2", 5)):
+    for name, mode in chosen:
         t0 = time.time()
         ang = rp.sample(s, w.seed, M, basis_mode=mode)
         phi = rp.propagate(s, B, ang, M, init_mode=1 if mode == 1 else 0, precision=args.precision)[0]
@@ -394,14 +400,15 @@ def sampling_variance(args):
                      "units": M // R}
         print(f"sampler {name}: {M} propagations x {B.shape[1]} fields in {time.time() - t0:.1f} s",
               file=sys.stderr, flush=True)
-    c = out["coherent"]
+    c = out[chosen[0][0]]
     rec = {"metric": "Monte Carlo samplers at equal cost (variance of the mean estimate)", "system": s.name,
+           "reference_sampler": chosen[0][0],
            "fields_mT": B[0].tolist(), "M": M, "dtype": f"f{args.precision}"}
     for name, v in out.items():
         rec[name] = {"group": v["group"], "independent_units": v["units"],
                      "per_sample_sigma": v["per_sample_sigma"].tolist(),
                      "mean": v["mean"].tolist(), "stderr": np.sqrt(v["est_var"]).tolist(),
-                     "variance_reduction_vs_coherent": (c["est_var"] / v["est_var"]).tolist(),
+                     "variance_reduction_vs_reference": (c["est_var"] / v["est_var"]).tolist(),
                      "mean_diff_over_eps": (np.abs(v["mean"] - c["mean"]) /
                                             np.sqrt(v["est_var"] + c["est_var"])).tolist()}
     print(json.dumps(rec), flush=True)
@@ -509,6 +516,10 @@ def main():
     ap.add_argument("--cv-no-augment", action="store_true", help="train without the field-axis rotations")
     ap.add_argument("--cv-quad", type=int, default=65536, help="samples for the mean of the network")
     ap.add_argument("--cv-eval", type=int, default=128, help="evaluation samples (pilot)")
+    ap.add_argument("--sampling-system", default="sweep", choices=["sweep", "paper"],
+                    help="sampling workload: the sweep system (0, 2.5, 10 mT) or the Sec. IV model (1, 3.5 mT)")
+    ap.add_argument("--samplers", default="coherent,jz,antithetic,oa3,oa2",
+                    help="sampling workload: comma-separated samplers, the first is the reference")
     ap.add_argument("--design", action="store_true",
                     help="sweep to eps <= 1e-3 with sign-flip design sampling (FP32) against plain FP64")
     ap.add_argument("--design-mode", type=int, default=5, choices=[3, 4, 5], help="rp_sample design mode")
@@ -628,7 +639,9 @@ def main():
                      "traffic": measured_traffic(args.precision, int(nterms),
                                                  prof["elements"] / max(prof["term_launches"], 1)),
                      "algorithmic_bytes_per_launch": prof["elements"] * bpe / max(prof["term_launches"], 1),
-                     "kernel": "k_cheb_tile (Chebyshev term; three launch variants)", "avg_launch_us": prof["term_ms"] * 1e3 / max(prof["term_launches"], 1),
+                     "kernel": ("k_cheb_pair (Chebyshev term on index pairs" if args.precision == 32 else
+                                "k_cheb_tile (Chebyshev term") + "; three launch variants)",
+                     "avg_launch_us": prof["term_ms"] * 1e3 / max(prof["term_launches"], 1),
                      "bytes_per_element_term": bpe, "terms_per_step": nterms,
                      "term_time_frac": prof["term_ms"] / max(prof["total_ms"], 1e-9),
                      "quad_time_frac": prof["quad_ms"] / max(prof["total_ms"], 1e-9)},

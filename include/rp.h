@@ -108,6 +108,10 @@ typedef struct rp_opts {
    for comparison with the default propagator (every job of a call does the same launches,
    each with its own step length; the small Krylov algebra runs on the host in FP64). */
 #define RP_FLAG_ARNOLDI 32
+/* opts->flags: run the complex-FP32 Chebyshev terms with one nuclear index per thread (the
+   256-index tile kernel, 8-byte accesses) instead of two per thread with 16-byte accesses.
+   Same sums in the same order; for comparison. */
+#define RP_FLAG_TERM_SCALAR 64
 
 /*
  * rp_sample -- directions of the nuclear coherent states (Eq. 18: uniform on

@@ -21,6 +21,7 @@
 #include <map>
 #include <numeric>
 #include <string>
+#include <type_traits>
 #include <thread>
 #include <type_traits>
 #include <vector>
@@ -265,13 +266,12 @@ __device__ __forceinline__ void flip_half(bool r1, int bit, R f, cx<R> p0, cx<R>
   }
 }
 
-// Everything after H x: diagonal, exchange, i beta P_S, shift and scale, recurrence,
-// stores of phi_{n+1}, its singlet amplitude and the accumulator.
-template <typename R, int MODE, bool NT>
-__device__ __forceinline__ void finish_term(const TermArgs<R> &ta, const SysArgs<R> &sa, const FieldDev<R> &fp,
-                                            int fi, int64_t job, int64_t M, R h1, R h2, cx<R> x0, cx<R> x1,
-                                            cx<R> x2, cx<R> x3, cx<R> o0, cx<R> o1, cx<R> o2, cx<R> o3,
-                                            cx<R> y0, cx<R> y1, cx<R> y2, cx<R> y3) {
+// Everything after H x for one nuclear index: diagonal, exchange, i beta P_S, shift and
+// scale, recurrence.  Returns the four components of phi_{n+1}.
+template <typename R, int MODE>
+__device__ __forceinline__ void term_z(const SysArgs<R> &sa, const FieldDev<R> &fp, R h1, R h2, cx<R> x0, cx<R> x1,
+                                       cx<R> x2, cx<R> x3, cx<R> o0, cx<R> o1, cx<R> o2, cx<R> o3, cx<R> y0,
+                                       cx<R> y1, cx<R> y2, cx<R> y3, cx<R> &z0, cx<R> &z1, cx<R> &z2, cx<R> &z3) {
   // Diagonal: omega (s1 + s2) + s1 h1 + s2 h2 + 2 J s1 s2 with s = +-1/2.
   const R hs = R(0.5) * (h1 + h2), hd = R(0.5) * (h1 - h2), hj = R(0.5) * sa.J;
   y0 = cadd(y0, cscale(fp.omega + hs + hj, x0));
@@ -285,16 +285,34 @@ __device__ __forceinline__ void finish_term(const TermArgs<R> &ta, const SysArgs
   y2 = csub(y2, ibt);
   const cx<R> c = {fp.c_re, fp.c_im};
   const R s = MODE == kFirst ? fp.s1 : fp.s2;
-  cx<R> z0 = cscale(s, csub(y0, cmul(c, x0)));
-  cx<R> z1 = cscale(s, csub(y1, cmul(c, x1)));
-  cx<R> z2 = cscale(s, csub(y2, cmul(c, x2)));
-  cx<R> z3 = cscale(s, csub(y3, cmul(c, x3)));
+  z0 = cscale(s, csub(y0, cmul(c, x0)));
+  z1 = cscale(s, csub(y1, cmul(c, x1)));
+  z2 = cscale(s, csub(y2, cmul(c, x2)));
+  z3 = cscale(s, csub(y3, cmul(c, x3)));
   if (MODE != kFirst) {
     z0 = csub(z0, o0);
     z1 = csub(z1, o1);
     z2 = csub(z2, o2);
     z3 = csub(z3, o3);
   }
+}
+
+// New accumulator value of one component: first term a_0 phi_0 + a_1 phi_1; every third
+// term acc + a_{n-1} phi_{n-1} + a_n phi_n + a_{n+1} phi_{n+1}.
+template <typename R, int MODE>
+__device__ __forceinline__ cx<R> acc_value(cx<R> am, cx<R> a0, cx<R> ap, cx<R> v, cx<R> o, cx<R> x, cx<R> z) {
+  if (MODE == kFirst) return cadd(cmul(am, x), cmul(a0, z));
+  return cadd(v, cadd(cadd(cmul(am, o), cmul(a0, x)), cmul(ap, z)));
+}
+
+// term_z, then the stores of phi_{n+1}, its singlet amplitude and the accumulator.
+template <typename R, int MODE, bool NT>
+__device__ __forceinline__ void finish_term(const TermArgs<R> &ta, const SysArgs<R> &sa, const FieldDev<R> &fp,
+                                            int fi, int64_t job, int64_t M, R h1, R h2, cx<R> x0, cx<R> x1,
+                                            cx<R> x2, cx<R> x3, cx<R> o0, cx<R> o1, cx<R> o2, cx<R> o3,
+                                            cx<R> y0, cx<R> y1, cx<R> y2, cx<R> y3) {
+  cx<R> z0, z1, z2, z3;
+  term_z<R, MODE>(sa, fp, h1, h2, x0, x1, x2, x3, o0, o1, o2, o3, y0, y1, y2, y3, z0, z1, z2, z3);
   const int64_t Z = sa.Z;
   const int64_t e = job * Z * 4 + M;
   cx<R> *O = ta.phio + e;
@@ -305,22 +323,22 @@ __device__ __forceinline__ void finish_term(const TermArgs<R> &ta, const SysArgs
   st_nt<true>(ta.dnext + job * sa.Z + M, csub(z1, z2));
   const cx<R> *cf = ta.coef + (int64_t)fi * ta.n_terms;
   cx<R> *A = ta.acc + e;
+  const cx<R> zero = {R(0), R(0)};
   if (MODE == kFirst) {
     const cx<R> a0 = cf[0], a1 = cf[1];
-    st_nt<NT>(A, cadd(cmul(a0, x0), cmul(a1, z0)));
-    st_nt<NT>(A + Z, cadd(cmul(a0, x1), cmul(a1, z1)));
-    st_nt<NT>(A + 2 * Z, cadd(cmul(a0, x2), cmul(a1, z2)));
-    st_nt<NT>(A + 3 * Z, cadd(cmul(a0, x3), cmul(a1, z3)));
+    st_nt<NT>(A, acc_value<R, MODE>(a0, a1, zero, zero, zero, x0, z0));
+    st_nt<NT>(A + Z, acc_value<R, MODE>(a0, a1, zero, zero, zero, x1, z1));
+    st_nt<NT>(A + 2 * Z, acc_value<R, MODE>(a0, a1, zero, zero, zero, x2, z2));
+    st_nt<NT>(A + 3 * Z, acc_value<R, MODE>(a0, a1, zero, zero, zero, x3, z3));
     st_nt<true>(ta.dfirst + job * sa.Z + M, csub(x1, x2));
   } else if (MODE == kAcc3) {
-    // acc += a_{n-1} phi_{n-1} + a_n phi_n + a_{n+1} phi_{n+1}
     const cx<R> am = cf[ta.n - 1], a0 = cf[ta.n], ap = cf[ta.n + 1];
     const cx<R> v0 = ld_nt<NT>(A), v1 = ld_nt<NT>(A + Z), v2 = ld_nt<NT>(A + 2 * Z),
                 v3 = ld_nt<NT>(A + 3 * Z);
-    st_nt<NT>(A, cadd(v0, cadd(cadd(cmul(am, o0), cmul(a0, x0)), cmul(ap, z0))));
-    st_nt<NT>(A + Z, cadd(v1, cadd(cadd(cmul(am, o1), cmul(a0, x1)), cmul(ap, z1))));
-    st_nt<NT>(A + 2 * Z, cadd(v2, cadd(cadd(cmul(am, o2), cmul(a0, x2)), cmul(ap, z2))));
-    st_nt<NT>(A + 3 * Z, cadd(v3, cadd(cadd(cmul(am, o3), cmul(a0, x3)), cmul(ap, z3))));
+    st_nt<NT>(A, acc_value<R, MODE>(am, a0, ap, v0, o0, x0, z0));
+    st_nt<NT>(A + Z, acc_value<R, MODE>(am, a0, ap, v1, o1, x1, z1));
+    st_nt<NT>(A + 2 * Z, acc_value<R, MODE>(am, a0, ap, v2, o2, x2, z2));
+    st_nt<NT>(A + 3 * Z, acc_value<R, MODE>(am, a0, ap, v3, o3, x3, z3));
   }
 }
 
@@ -481,6 +499,199 @@ __global__ __launch_bounds__(256) void k_cheb_tile(TermArgs<R> ta, SysArgs<R> sa
   }
 }
 
+// ---- complex-FP32 term kernel on index pairs
+// Two consecutive complex FP32 numbers as one 16-byte vector.
+using f4 = float __attribute__((ext_vector_type(4)));
+template <bool ON>
+__device__ __forceinline__ f4 ld4(const cx<float> *p) {
+  const f4 *q = reinterpret_cast<const f4 *>(p);
+  if constexpr (ON) return __builtin_nontemporal_load(q);
+  else return *q;
+}
+template <bool ON>
+__device__ __forceinline__ void st4(cx<float> *p, cx<float> a, cx<float> b) {
+  f4 v;
+  v.x = a.x;
+  v.y = a.y;
+  v.z = b.x;
+  v.w = b.y;
+  if constexpr (ON) __builtin_nontemporal_store(v, reinterpret_cast<f4 *>(p));
+  else *reinterpret_cast<f4 *>(p) = v;
+}
+__device__ __forceinline__ cx<float> lo(f4 v) { return {v.x, v.y}; }
+__device__ __forceinline__ cx<float> hi(f4 v) { return {v.z, v.w}; }
+
+// H x accumulated for one nuclear index: the four components and the diagonal sums of the
+// two radicals.
+struct PairAcc {
+  cx<float> y0, y1, y2, y3;
+  float h1, h2;
+};
+
+// One spin-1/2 axis: the diagonal term a_k m_k and the flip-flop term from the partner's two
+// components (p0, p1), with the radical chosen on values (no output chosen by a branch, so
+// both PairAcc of a thread stay in registers).
+__device__ __forceinline__ void pair_axis(PairAcc &A, bool r1, int bit, float a, float f, cx<float> p0,
+                                          cx<float> p1) {
+  const float am = a * (bit ? -0.5f : 0.5f);
+  A.h1 += r1 ? am : 0.0f;
+  A.h2 += r1 ? 0.0f : am;
+  const cx<float> u0 = cscale(f, p0), u1 = cscale(f, p1), z = {0.0f, 0.0f};
+  const cx<float> lo0 = csel(bit, u0, z), lo1 = csel(bit, u1, z), hi0 = csel(bit, z, u0), hi1 = csel(bit, z, u1);
+  A.y0 = cadd(A.y0, lo0);
+  A.y1 = cadd(A.y1, r1 ? lo1 : hi0);
+  A.y2 = cadd(A.y2, r1 ? hi0 : lo1);
+  A.y3 = cadd(A.y3, hi1);
+}
+
+// The two components of the partner that feed this index along a spin-1/2 axis: for the
+// radical-1 electron, (aa, ab) or (ba, bb) of the partner; for radical 2, (aa, ba) or (ab, bb).
+__device__ __forceinline__ int pair_c0(bool r1, int bit) { return r1 ? 2 * bit : bit; }
+__device__ __forceinline__ int pair_c1(bool r1, int bit) { return r1 ? 2 * bit + 1 : bit + 2; }
+
+// One Chebyshev term (complex FP32) with the same 256-index tile as k_cheb_tile, run by 128
+// threads that own two consecutive indices M, M + 1 each.  Every global access is a 16-byte
+// vector (two complex numbers), the partner along axis 0 is the thread's other index, the
+// partners along axes 1..7 come from LDS (16-byte reads) and those along the slow axes from
+// global memory; higher spins follow as in k_cheb_tile.  Needs at least 8 spin-1/2 nuclei
+// first (Z a multiple of 256).
+constexpr int kPairThreads = kBlock / 2;
+constexpr int kPairBatch = 4;   // slow-axis partner pairs loaded together
+template <int MODE, bool NT>
+__global__ __launch_bounds__(kPairThreads) void k_cheb_pair(TermArgs<float> ta, SysArgs<float> sa) {
+  __shared__ f4 tile[4 * kPairThreads];
+  __shared__ double lds[2];
+  const int64_t total = (int64_t)ta.njobs * ta.nbx;
+  const int64_t L = ta.remap ? xcd_remap(blockIdx.x, total) : (int64_t)blockIdx.x;
+  const int64_t job = L / ta.nbx, bx = L - job * ta.nbx;
+  const int tid = threadIdx.x;
+  const int64_t M = bx * kBlock + 2 * tid;
+  const int fi = ta.job_field[job];
+  const FieldDev<float> fp = ta.fields[fi];
+  const int64_t Z = sa.Z;
+  const cx<float> *X = ta.phin + job * Z * 4;
+  f4 xv[4], ov[4] = {};
+  for (int e = 0; e < 4; ++e) xv[e] = ld4<false>(X + e * Z + M);
+  if (MODE != kFirst) {
+    const cx<float> *O = ta.phio + job * Z * 4 + M;
+    for (int e = 0; e < 4; ++e) ov[e] = ld4<NT>(O + e * Z);
+  }
+  for (int e = 0; e < 4; ++e) tile[e * kPairThreads + tid] = xv[e];
+  __syncthreads();
+  const cx<float> zero = {0.0f, 0.0f};
+  PairAcc A = {zero, zero, zero, zero, 0.0f, 0.0f}, B = A;   // index M, M + 1
+  {  // axis 0: the other index of this thread
+    const bool r1 = sa.rad[0] == 0;
+    const float a = sa.a[0], f = sa.f[0][0];
+    pair_axis(A, r1, 0, a, f, hi(xv[pair_c0(r1, 0)]), hi(xv[pair_c1(r1, 0)]));
+    pair_axis(B, r1, 1, a, f, lo(xv[pair_c0(r1, 1)]), lo(xv[pair_c1(r1, 1)]));
+  }
+#pragma unroll
+  for (int k = 1; k < 8; ++k) {   // axes 1..7: thread bit k-1, both indices share it
+    const int bit = (tid >> (k - 1)) & 1;
+    const int pt = tid ^ (1 << (k - 1));
+    const bool r1 = sa.rad[k] == 0;
+    const f4 q0 = tile[pair_c0(r1, bit) * kPairThreads + pt], q1 = tile[pair_c1(r1, bit) * kPairThreads + pt];
+    pair_axis(A, r1, bit, sa.a[k], sa.f[k][0], lo(q0), lo(q1));
+    pair_axis(B, r1, bit, sa.a[k], sa.f[k][0], hi(q0), hi(q1));
+  }
+  const int nh = sa.nhalf;
+  for (int k0 = 8; k0 < nh; k0 += kPairBatch) {
+    f4 pa[kPairBatch], pb[kPairBatch];
+#pragma unroll
+    for (int j = 0; j < kPairBatch; ++j) {
+      const int k = k0 + j;
+      if (k < nh) {
+        const int bit = (int)((M >> k) & 1);
+        const bool r1 = sa.rad[k] == 0;
+        const int64_t P = M ^ ((int64_t)1 << k);
+        pa[j] = ld4<false>(X + pair_c0(r1, bit) * Z + P);
+        pb[j] = ld4<false>(X + pair_c1(r1, bit) * Z + P);
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < kPairBatch; ++j) {
+      const int k = k0 + j;
+      if (k < nh) {
+        const int bit = (int)((M >> k) & 1);
+        const bool r1 = sa.rad[k] == 0;
+        pair_axis(A, r1, bit, sa.a[k], sa.f[k][0], lo(pa[j]), lo(pb[j]));
+        pair_axis(B, r1, bit, sa.a[k], sa.f[k][0], hi(pa[j]), hi(pb[j]));
+      }
+    }
+  }
+  // Higher spins: digits uniform over the workgroup (strides are multiples of 256); a missing
+  // partner gets coefficient 0 and reads this thread's own pair.
+  int64_t rem = (bx * kBlock) >> nh;
+  for (int k = nh; k < sa.N; ++k) {
+    const int dk = sa.d[k];
+    const int64_t q = rem / dk;
+    const int n = __builtin_amdgcn_readfirstlane((int)(rem - q * dk));
+    rem = q;
+    const int64_t st = sa.stride[k];
+    const bool r1 = sa.rad[k] == 0;
+    const float mk = 0.5f * (float)(dk - 1) - (float)n;
+    const float am = sa.a[k] * mk;
+    A.h1 += r1 ? am : 0.0f;
+    A.h2 += r1 ? 0.0f : am;
+    B.h1 += r1 ? am : 0.0f;
+    B.h2 += r1 ? 0.0f : am;
+    const int64_t Pm = n > 0 ? M - st : M, Pp = n < dk - 1 ? M + st : M;
+    const float fm = n > 0 ? sa.f[k][n - 1] : 0.0f;
+    const float fpl = n < dk - 1 ? sa.f[k][n] : 0.0f;
+    // minus partner (digit n-1) feeds the alpha components from beta ones; plus partner
+    // (digit n+1) feeds beta components from alpha ones
+    const f4 pm0 = ld4<false>(X + (r1 ? 2 : 1) * Z + Pm), pm1 = ld4<false>(X + 3 * Z + Pm);
+    const f4 pp0 = ld4<false>(X + Pp), pp1 = ld4<false>(X + (r1 ? 1 : 2) * Z + Pp);
+    A.y0 = cadd(A.y0, cscale(fm, lo(pm0)));
+    B.y0 = cadd(B.y0, cscale(fm, hi(pm0)));
+    A.y3 = cadd(A.y3, cscale(fpl, lo(pp1)));
+    B.y3 = cadd(B.y3, cscale(fpl, hi(pp1)));
+    const cx<float> ua = cscale(fm, lo(pm1)), ub = cscale(fm, hi(pm1));
+    const cx<float> va = cscale(fpl, lo(pp0)), vb = cscale(fpl, hi(pp0));
+    A.y1 = cadd(A.y1, r1 ? ua : va);
+    A.y2 = cadd(A.y2, r1 ? va : ua);
+    B.y1 = cadd(B.y1, r1 ? ub : vb);
+    B.y2 = cadd(B.y2, r1 ? vb : ub);
+  }
+  // phi_{n+1}, its singlet amplitude and the accumulator, two indices per 16-byte access
+  cx<float> za[4], zb[4];
+  term_z<float, MODE>(sa, fp, A.h1, A.h2, lo(xv[0]), lo(xv[1]), lo(xv[2]), lo(xv[3]), lo(ov[0]), lo(ov[1]),
+                      lo(ov[2]), lo(ov[3]), A.y0, A.y1, A.y2, A.y3, za[0], za[1], za[2], za[3]);
+  term_z<float, MODE>(sa, fp, B.h1, B.h2, hi(xv[0]), hi(xv[1]), hi(xv[2]), hi(xv[3]), hi(ov[0]), hi(ov[1]),
+                      hi(ov[2]), hi(ov[3]), B.y0, B.y1, B.y2, B.y3, zb[0], zb[1], zb[2], zb[3]);
+  const int64_t e0 = job * Z * 4 + M;
+  cx<float> *O = ta.phio + e0;
+  for (int e = 0; e < 4; ++e) st4<NT>(O + e * Z, za[e], zb[e]);
+  st4<true>(ta.dnext + job * Z + M, csub(za[1], za[2]), csub(zb[1], zb[2]));
+  const cx<float> *cf = ta.coef + (int64_t)fi * ta.n_terms;
+  cx<float> *Ac = ta.acc + e0;
+  if (MODE == kFirst) {
+    const cx<float> a0 = cf[0], a1 = cf[1];
+    for (int e = 0; e < 4; ++e)
+      st4<NT>(Ac + e * Z, acc_value<float, MODE>(a0, a1, zero, zero, zero, lo(xv[e]), za[e]),
+              acc_value<float, MODE>(a0, a1, zero, zero, zero, hi(xv[e]), zb[e]));
+    st4<true>(ta.dfirst + job * Z + M, csub(lo(xv[1]), lo(xv[2])), csub(hi(xv[1]), hi(xv[2])));
+  } else if (MODE == kAcc3) {
+    const cx<float> am = cf[ta.n - 1], a0 = cf[ta.n], ap = cf[ta.n + 1];
+    f4 v[4];
+    for (int e = 0; e < 4; ++e) v[e] = ld4<NT>(Ac + e * Z);
+    for (int e = 0; e < 4; ++e)
+      st4<NT>(Ac + e * Z, acc_value<float, MODE>(am, a0, ap, lo(v[e]), lo(ov[e]), lo(xv[e]), za[e]),
+              acc_value<float, MODE>(am, a0, ap, hi(v[e]), hi(ov[e]), hi(xv[e]), zb[e]));
+  }
+  if (MODE == kFirst) {
+    double nrm = 0.0;
+    for (int e = 0; e < 4; ++e)
+      nrm += (double)xv[e].x * xv[e].x + (double)xv[e].y * xv[e].y + (double)xv[e].z * xv[e].z +
+             (double)xv[e].w * xv[e].w;
+    nrm = warp_sum(nrm);
+    if ((tid & 63) == 0) lds[tid >> 6] = nrm;
+    __syncthreads();
+    if (tid == 0) ta.part_norm[job * ta.nbx + bx] = lds[0] + lds[1];
+  }
+}
+
 // One Chebyshev term for any mix of spins (mixed-radix digits, partners from global memory).
 template <typename R, int MODE, bool NT>
 __global__ __launch_bounds__(256) void k_cheb_gen(TermArgs<R> ta, SysArgs<R> sa) {
@@ -612,24 +823,33 @@ __global__ __launch_bounds__(256) void k_quad(QuadArgs<R> qa) {
   }
 }
 
+// Term kernel variants: any mix of spins, the 256-index tile, and the tile on index pairs.
+enum TermKernel { kTermGen = 0, kTermTile = 1, kTermPair = 2 };
+
 template <typename R, int MODE, bool NT>
-static void launch_term_t(bool tiled, unsigned grid, hipStream_t st, const TermArgs<R> &ta, const SysArgs<R> &sa) {
-  if (tiled)
-    hipLaunchKernelGGL((k_cheb_tile<R, MODE, NT>), dim3(grid), dim3(kBlock), 0, st, ta, sa);
-  else
+static void launch_term_t(int kind, unsigned grid, hipStream_t st, const TermArgs<R> &ta, const SysArgs<R> &sa) {
+  if constexpr (std::is_same<R, float>::value) {
+    if (kind == kTermPair) {
+      hipLaunchKernelGGL((k_cheb_pair<MODE, NT>), dim3(grid), dim3(kPairThreads), 0, st, ta, sa);
+      return;
+    }
+  }
+  if (kind == kTermGen)
     hipLaunchKernelGGL((k_cheb_gen<R, MODE, NT>), dim3(grid), dim3(kBlock), 0, st, ta, sa);
+  else
+    hipLaunchKernelGGL((k_cheb_tile<R, MODE, NT>), dim3(grid), dim3(kBlock), 0, st, ta, sa);
 }
 
 template <typename R>
-static void launch_term(int mode, bool tiled, bool nt, unsigned grid, hipStream_t st, const TermArgs<R> &ta,
+static void launch_term(int mode, int kind, bool nt, unsigned grid, hipStream_t st, const TermArgs<R> &ta,
                         const SysArgs<R> &sa) {
   switch (mode * 2 + (nt ? 1 : 0)) {
-    case kFirst * 2: launch_term_t<R, kFirst, false>(tiled, grid, st, ta, sa); break;
-    case kFirst * 2 + 1: launch_term_t<R, kFirst, true>(tiled, grid, st, ta, sa); break;
-    case kPlain * 2: launch_term_t<R, kPlain, false>(tiled, grid, st, ta, sa); break;
-    case kPlain * 2 + 1: launch_term_t<R, kPlain, true>(tiled, grid, st, ta, sa); break;
-    case kAcc3 * 2: launch_term_t<R, kAcc3, false>(tiled, grid, st, ta, sa); break;
-    default: launch_term_t<R, kAcc3, true>(tiled, grid, st, ta, sa); break;
+    case kFirst * 2: launch_term_t<R, kFirst, false>(kind, grid, st, ta, sa); break;
+    case kFirst * 2 + 1: launch_term_t<R, kFirst, true>(kind, grid, st, ta, sa); break;
+    case kPlain * 2: launch_term_t<R, kPlain, false>(kind, grid, st, ta, sa); break;
+    case kPlain * 2 + 1: launch_term_t<R, kPlain, true>(kind, grid, st, ta, sa); break;
+    case kAcc3 * 2: launch_term_t<R, kAcc3, false>(kind, grid, st, ta, sa); break;
+    default: launch_term_t<R, kAcc3, true>(kind, grid, st, ta, sa); break;
   }
 }
 
@@ -1050,7 +1270,8 @@ static int read_opts(const rp_opts *o, Opts &out) {
       return fail(RP_EINVAL, "negative option");
     if (o->max_growth != 0 && !(o->max_growth >= 2.0)) return fail(RP_EINVAL, "max_growth must be >= 2");
     const int known =
-        RP_FLAG_PROFILE | RP_FLAG_TILED | RP_FLAG_XCD_LOCAL | RP_FLAG_XCD_SPREAD | RP_FLAG_NO_GRAPH | RP_FLAG_ARNOLDI;
+        RP_FLAG_PROFILE | RP_FLAG_TILED | RP_FLAG_XCD_LOCAL | RP_FLAG_XCD_SPREAD | RP_FLAG_NO_GRAPH | RP_FLAG_ARNOLDI |
+        RP_FLAG_TERM_SCALAR;
     if ((o->flags & ~known) != 0) return fail(RP_EINVAL, "unknown flags");
     if (o->krylov_dim != 0 && (o->krylov_dim < 2 || o->krylov_dim > 32))
       return fail(RP_EINVAL, "krylov_dim must be 0 or in [2, 32]");
@@ -1287,6 +1508,11 @@ static int propagate_system(const SystemSpec &spec, const double *B, int nB, con
   // survive there until the next launch anyway, and the hint leaves the L2 to the partner
   // tiles of phi_n.  The singlet amplitudes, read only by the quadrature, always stream.
   const bool stream_nt = 3 * chunk * vec_bytes > ((int64_t)256 << 20);
+  // Term kernel: index pairs (complex FP32, at least 8 leading spin-1/2 nuclei), else the
+  // 256-index tile, else the generic form.
+  int term_kind = sa.tiled ? kTermTile : kTermGen;
+  if (std::is_same<R, float>::value && sa.tiled && sa.nhalf >= 8 && !(op.flags & RP_FLAG_TERM_SCALAR))
+    term_kind = kTermPair;
   const double rtol = op.precision == 64 ? 1e-9 : 1e-4;
   // Graph replay of the step launches (not while profiling: the events are per launch).
   const bool use_graph = !log.on && !(op.flags & RP_FLAG_NO_GRAPH);
@@ -1347,7 +1573,7 @@ static int propagate_system(const SystemSpec &spec, const double *B, int nB, con
       ta.dfirst = D;
       const double eb = (double)sizeof(R) / 4.0;   // bytes per element, in units of complex-FP32 bytes
       log.mark(st);
-      launch_term<R>(kFirst, sa.tiled != 0, stream_nt, grid, st, ta, sa);
+      launch_term<R>(kFirst, term_kind, stream_nt, grid, st, ta, sa);
       double bytes = 28.0 * eb;
       for (int n = 1; n + 1 < nt; ++n) {
         // phi_{n+1} = 2 Gh phi_n - phi_{n-1}, written over phi_{n-1}; every third launch also adds
@@ -1357,7 +1583,7 @@ static int propagate_system(const SystemSpec &spec, const double *B, int nB, con
         ta.n = n;
         ta.dnext = D + (int64_t)(n + 1) * slab;
         const bool acc3 = (n % 3) == 0;
-        launch_term<R>(acc3 ? kAcc3 : kPlain, sa.tiled != 0, stream_nt, grid, st, ta, sa);
+        launch_term<R>(acc3 ? kAcc3 : kPlain, term_kind, stream_nt, grid, st, ta, sa);
         bytes += (acc3 ? 42.0 : 26.0) * eb;
       }
       log.mark(st);

@@ -47,6 +47,7 @@ RP_FLAG_XCD_LOCAL = 4
 RP_FLAG_XCD_SPREAD = 8
 RP_FLAG_NO_GRAPH = 16
 RP_FLAG_ARNOLDI = 32
+RP_FLAG_TERM_SCALAR = 64
 
 
 def lib():
@@ -154,7 +155,7 @@ def sample(system: SpinSystem, seed, M, first=0, stream_id=0, basis_mode=0, out=
 
 def propagate(systems, B_mT, angles, M, precision=64, init_mode=0, tol=0.0, rdt=0.0, r_scale=0.0,
               workspace_bytes=0, out=None, profile=False, tiled=False, xcd=None, graph=True, max_growth=0.0,
-              arnoldi=False, krylov_dim=0):
+              arnoldi=False, krylov_dim=0, term_scalar=False):
     """rp_propagate: single-wavepacket yields [n_sys][nB][M] (float64 CUDA tensor).
 
     ``systems`` is a SpinSystem or a list; ``B_mT`` is [n_sys][nB] (host);
@@ -174,6 +175,7 @@ def propagate(systems, B_mT, angles, M, precision=64, init_mode=0, tol=0.0, rdt=
     ang = _dev_ptr(angles, torch.float64) if angles is not None and angles.numel() else None
     flags = (RP_FLAG_PROFILE if profile else 0) | (RP_FLAG_TILED if tiled else 0)
     flags |= (0 if graph else RP_FLAG_NO_GRAPH) | (RP_FLAG_ARNOLDI if arnoldi else 0)
+    flags |= RP_FLAG_TERM_SCALAR if term_scalar else 0
     if xcd == "local":
         flags |= RP_FLAG_XCD_LOCAL
     elif xcd == "spread":
