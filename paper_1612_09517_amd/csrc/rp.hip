@@ -556,7 +556,7 @@ __device__ __forceinline__ int pair_c1(bool r1, int bit) { return r1 ? 2 * bit +
 // global memory; higher spins follow as in k_cheb_tile.  Needs at least 8 spin-1/2 nuclei
 // first (Z a multiple of 256).
 constexpr int kPairThreads = kBlock / 2;
-constexpr int kPairBatch = 4;   // slow-axis partner pairs loaded together
+constexpr int kPairBatch = 8;   // slow-axis partner pairs loaded together
 template <int MODE, bool NT>
 __global__ __launch_bounds__(kPairThreads) void k_cheb_pair(TermArgs<float> ta, SysArgs<float> sa) {
   __shared__ f4 tile[4 * kPairThreads];
