@@ -282,10 +282,11 @@ def design_headline(args):
     in complex FP32, measured end to end: groups are added to the fields whose standard error
     (over group means) is above eps until none is, starting from --design-groups groups.
     Plain FP64 and plain FP32 Monte Carlo wall times follow from measured rates and the
-    per-sample deviation of a plain pilot, as M_needed * fields / rate.  Same workload as --cv."""
+    per-sample deviation of a plain pilot, as M_needed * fields / rate.  The workload of --cv,
+    or with --design-workload sweep the bench sweep (64 fields 0..10 mT)."""
     import torch
     from paper_1612_09517_amd import rp, workloads
-    w = workloads.cv_c5()
+    w = workloads.sweep_c2() if args.design_workload == "sweep" else workloads.cv_c5()
     s = w.systems[0]
     B = w.fields_mT[0]
     nB = len(B)
@@ -315,7 +316,12 @@ def design_headline(args):
         G = int(np.max(need[todo] - done[todo]))
         first = int(done[todo].max()) * R   # fresh groups for every field in this round
         a = rp.sample(s, w.seed, G * R, first=first, basis_mode=mode)
-        g = rp.group_mean(rp.propagate(s, B[todo][None, :], a, G * R, precision=32)[0], R)
+        parts = []
+        for c0 in range(0, todo.size, 16):          # 16 fields per call, with progress
+            fs = todo[c0:c0 + 16]
+            parts.append(rp.group_mean(rp.propagate(s, B[fs][None, :], a, G * R, precision=32)[0], R))
+            say(f"round {rounds + 1}: fields {c0 + fs.size}/{todo.size}")
+        g = torch.cat(parts)
         props += G * R * todo.size
         for j, f in enumerate(todo):
             gm[f] = g[j] if gm[f] is None else torch.cat([gm[f], g[j]])
@@ -331,7 +337,8 @@ def design_headline(args):
     Me = args.cv_eval
     t0 = time.perf_counter()
     a_ev = rp.sample(s, w.seed + 1, Me)
-    phi_ev = rp.propagate(s, B[None, :], a_ev, Me, precision=32)[0]
+    phi_ev = torch.cat([rp.propagate(s, B[None, c0:c0 + 16], a_ev, Me, precision=32)[0]
+                        for c0 in range(0, nB, 16)])
     sync()
     rate32 = Me * nB / (time.perf_counter() - t0)
     m_pl, e_pl = (x.cpu().numpy() for x in rp.yield_stats(phi_ev))
@@ -349,7 +356,8 @@ def design_headline(args):
     vr = sig_pl ** 2 / (err_d ** 2 * done * R)
     rec = {"metric": "sweep wall time at sigma(Phi_S)<=1e-3: FP32 + sign-flip design vs plain FP64 MC",
            "value": wall_design, "unit": "s", "higher_is_better": False, "n_gpus": 1, "data": "synthetic",
-           "dtype": "f32", "config": {"workload": w.name + ": N=14 spin-1/2, Z=16384, 32 fields 0..5 mT",
+           "dtype": "f32", "config": {"workload": w.name + f": N=14 spin-1/2, Z=16384, {nB} fields "
+                                                   f"{B[0]:g}..{B[-1]:g} mT, T={s.T_us:g} us",
                                       "design_mode": mode, "samples_per_group": R,
                                       "initial_groups": args.design_groups, "plain_pilot_samples": Me},
            "plain_fp64_wall_s": wall64, "plain_fp32_wall_s": wall32, "speedup_vs_fp64": wall64 / wall_design,
@@ -524,6 +532,8 @@ def main():
                     help="sweep to eps <= 1e-3 with sign-flip design sampling (FP32) against plain FP64")
     ap.add_argument("--design-mode", type=int, default=5, choices=[3, 4, 5], help="rp_sample design mode")
     ap.add_argument("--design-groups", type=int, default=8, help="design groups per field to start with")
+    ap.add_argument("--design-workload", default="cv", choices=["cv", "sweep"],
+                    help="--design on the control-variate workload (32 fields) or the bench sweep (64 fields)")
     ap.add_argument("--summarize", default="",
                     help="print a per-kernel summary of a rocprofv3 CSV directory and exit")
     args = ap.parse_args()
