@@ -2624,6 +2624,7 @@ extern "C" int rp_group_mean(const double *phi, int32_t nB, int64_t M, int64_t g
   if (nB == 0 || M == 0) return RP_OK;
   if (!phi || !out) return fail(RP_EINVAL, "null pointer");
   const int64_t n_out = (int64_t)nB * (M / group);
+  if (n_out > ((int64_t)1 << 38)) return fail(RP_EINVAL, "too many groups");
   hipLaunchKernelGGL(k_group_mean, dim3(grid1(n_out)), dim3(256), 0, (hipStream_t)hip_stream, phi, n_out, group,
                      out);
   HIPCHK(hipGetLastError());
