@@ -1945,7 +1945,7 @@ extern "C" int rp_sample(const rp_system *s, uint64_t seed, uint32_t stream_id, 
   const int N = s->n_nuc[0] + s->n_nuc[1];
   if (M == 0 || N == 0) return RP_OK;
   if (!angles) return fail(RP_EINVAL, "null angles");
-  if (M > ((int64_t)1 << 40)) return fail(RP_EINVAL, "M too large");
+  if (M > ((int64_t)1 << 40) || M * N > ((int64_t)1 << 38)) return fail(RP_EINVAL, "M too large");
   SampleArgs a;
   std::memset(&a, 0, sizeof(a));
   a.angles = angles;
