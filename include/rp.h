@@ -81,6 +81,8 @@ typedef struct rp_opts {
                                over the dissipative strip of the spectrum; steps are shortened until
                                it holds (it limits the rounding error of the series).  0 selects
                                1e10 (64) or 1e6 (32); otherwise >= 2. */
+  int64_t ps_t_len;         /* time points per wavepacket in rp_propagate's ps_t (required, >= 1,
+                               when ps_t is not NULL; ignored otherwise) */
 } rp_opts;
 
 /* opts->flags: record HIP events around the Chebyshev-term launches of every step
@@ -172,7 +174,13 @@ int64_t rp_design_size(int32_t n_nuclei, int32_t basis_mode);
  *   M          samples per system
  *   opts       options (NULL = defaults)
  *   phi        device, [n_sys][nB][M] doubles, written
- *   ps_t       must be NULL (trajectory output is not implemented: RP_ENOTIMPL)
+ *   ps_t       device, [n_sys][nB][M][opts->ps_t_len] doubles, or NULL: the singlet
+ *              population <psi(t)|P_S|psi(t)> (Eq. 3 and Eq. 20 without the factor k_S; it
+ *              includes the loss of norm by recombination) at the start of every step,
+ *              t_j = j dt for j < min(ps_t_len, n_steps), with dt and n_steps of that system
+ *              and field as rp_plan_field reports them (info[3], info[4]); NaN for j >=
+ *              n_steps.  Written by the tiled kernels (small systems then run tiled too);
+ *              RP_ENOTIMPL with RP_FLAG_ARNOLDI (adaptive steps have no common time grid).
  *
  * Each wavepacket is propagated by a Chebyshev expansion of exp(-iGt),
  * G = H - iK, in steps of length dt; the time integral of P_S within each step

@@ -121,6 +121,9 @@ struct FinArgs {
   int32_t njobs;
   int32_t pad;
   double kS, kmin, rtol;
+  double *ps_t;            // singlet population at step starts, [outputs][ps_len], or null
+  const int64_t *dst;      // [jobs] output index of each job
+  int64_t ps_len;
 };
 
 // ---------------------------------------------------------------- LDS-resident propagation

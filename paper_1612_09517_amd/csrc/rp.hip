@@ -1071,19 +1071,22 @@ __global__ __launch_bounds__(MAXB) void k_resident(ResArgs<R> ra) {
 __global__ __launch_bounds__(256) void k_finalize(FinArgs fa) {
   __shared__ double lds[4];
   const int64_t job = blockIdx.x;
-  double y = 0.0, nrm = 0.0;
+  double y = 0.0, nrm = 0.0, ps = 0.0;
   for (int64_t b = threadIdx.x; b < fa.nbx; b += kBlock) {
     y += fa.part_q[(job * fa.nbx + b) * 2];
     nrm += fa.part_norm[job * fa.nbx + b];
+    if (fa.ps_t) ps += fa.part_q[(job * fa.nbx + b) * 2 + 1];
   }
   y = block_sum(y, lds);
   nrm = block_sum(nrm, lds);
+  if (fa.ps_t) ps = block_sum(ps, lds);
   if (threadIdx.x != 0) return;
   const int fi = fa.job_field[job];
   const int32_t step = fa.stepc[job];
   fa.stepc[job] = step + 1;
   const double decay = exp(-fa.kmin * step * fa.dt[fi]);
   fa.phi[job] += fa.kS * decay * y;
+  if (fa.ps_t && step < fa.ps_len) fa.ps_t[fa.dst[job] * fa.ps_len + step] = decay * ps;
   const double Nt = decay * nrm;           // population N(t_j) of the wavepacket
   if (!(Nt <= fa.prev_norm[job] * (1.0 + fa.rtol) + 1e-300) || !(y == y)) atomicOr(fa.flag, 1);
   fa.prev_norm[job] = Nt;
@@ -1256,6 +1259,7 @@ struct Opts {
   double tol = 0, rdt = 0, r_scale = 1.0, chol_tol = 0, max_growth = 0;
   bool tol_set = false;
   int64_t workspace = 0;
+  int64_t ps_len = 0;
 };
 
 static int read_opts(const rp_opts *o, Opts &out) {
@@ -1283,6 +1287,8 @@ static int read_opts(const rp_opts *o, Opts &out) {
     if (o->r_scale > 0) out.r_scale = o->r_scale;
     out.workspace = o->workspace_bytes;
     out.max_growth = o->max_growth;
+    if (o->ps_t_len < 0) return fail(RP_EINVAL, "negative ps_t_len");
+    out.ps_len = o->ps_t_len;
   }
   if (out.tol == 0) out.tol = out.precision == 64 ? 1e-14 : 1e-9;
   out.chol_tol = out.precision == 64 ? 1e-17 : 1e-12;
@@ -1356,7 +1362,8 @@ static unsigned grid1(int64_t n) { return (unsigned)((n + 255) / 256); }
 // Propagates every (field, sample) job of one system; writes phi_out[b][s] (device).
 template <typename R>
 static int propagate_system(const SystemSpec &spec, const double *B, int nB, const double *angles_dev,
-                            int64_t M, const Opts &op, double *phi_out, hipStream_t st, EventLog &log) {
+                            int64_t M, const Opts &op, double *phi_out, double *ps_out, hipStream_t st,
+                            EventLog &log) {
   std::vector<FieldPlan> plans;
   int rc = plan_all(spec, B, nB, op, plans);
   if (rc) return rc;
@@ -1478,6 +1485,11 @@ static int propagate_system(const SystemSpec &spec, const double *B, int nB, con
   HIPCHK(hipMemcpyAsync(bJs.p, job_sample.data(), total_jobs * 4, hipMemcpyHostToDevice, st));
   HIPCHK(hipMemcpyAsync(bDst.p, dst.data(), total_jobs * 8, hipMemcpyHostToDevice, st));
   HIPCHK(hipMemsetAsync(bFlag.p, 0, 16, st));
+  if (ps_out) {   // time points past a field's last step stay NaN
+    const int64_t n = total_jobs * op.ps_len;
+    hipLaunchKernelGGL(k_fill, dim3(grid1(n)), dim3(256), 0, st, ps_out, n, std::nan(""));
+    HIPCHK(hipGetLastError());
+  }
 
   // Coherent-state components of every sample (shared by all fields).
   if (N > 0 && M > 0) {
@@ -1627,6 +1639,9 @@ static int propagate_system(const SystemSpec &spec, const double *B, int nB, con
       fa.kS = spec.kS;
       fa.kmin = kmin;
       fa.rtol = rtol;
+      fa.ps_t = ps_out;
+      fa.dst = (const int64_t *)bDst.p + j0;
+      fa.ps_len = op.ps_len;
       hipLaunchKernelGGL(k_finalize, dim3((unsigned)active), dim3(kBlock), 0, st, fa);
     };
     // One captured graph per (active jobs, buffer parity) of this chunk, replayed every step.
@@ -2473,11 +2488,14 @@ extern "C" int rp_propagate(const rp_system *sys, int32_t n_sys, const double *B
   if (n_sys < 0 || nB < 0 || M < 0) return fail(RP_EINVAL, "negative count");
   if (n_sys == 0 || nB == 0 || M == 0) return RP_OK;
   if (!sys || !B_mT || !phi) return fail(RP_EINVAL, "null pointer");
-  if (ps_t) return fail(RP_ENOTIMPL, "trajectory output is not implemented");
   if (M > (int64_t)1 << 31) return fail(RP_EINVAL, "M too large");
   Opts op;
   int rc = read_opts(opts, op);
   if (rc) return rc;
+  if (ps_t && (op.flags & RP_FLAG_ARNOLDI))
+    return fail(RP_ENOTIMPL, "trajectory output needs the Chebyshev steps (not RP_FLAG_ARNOLDI)");
+  if (ps_t && op.ps_len < 1) return fail(RP_EINVAL, "ps_t needs opts->ps_t_len >= 1");
+  if (ps_t && (double)n_sys * nB * (double)M * (double)op.ps_len > 0x1p38) return fail(RP_EINVAL, "ps_t too large");
   for (int i = 0; i < n_sys; ++i) {
     rc = validate_system(&sys[i]);
     if (rc) return rc;
@@ -2531,7 +2549,7 @@ extern "C" int rp_propagate(const rp_system *sys, int32_t n_sys, const double *B
       o += M * N * 2;
       int64_t Z = 1;
       for (int k = 0; k < N; ++k) Z *= sys[i].two_I[k] + 1;
-      if (!(op.flags & RP_FLAG_TILED) && !log.on && Z <= zmax) resident.push_back(i);
+      if (!(op.flags & RP_FLAG_TILED) && !log.on && !ps_t && Z <= zmax) resident.push_back(i);
     }
   }
   if (!resident.empty()) {
@@ -2551,8 +2569,10 @@ extern "C" int rp_propagate(const rp_system *sys, int32_t n_sys, const double *B
                                            s->T_us, gamma_of(s)));
     const double *ang = angles ? angles + aoff : nullptr;
     double *out = phi + (int64_t)i * nB * M;
-    rc = op.precision == 64 ? propagate_system<double>(spec, B_mT + (int64_t)i * nB, nB, ang, M, op, out, st, log)
-                            : propagate_system<float>(spec, B_mT + (int64_t)i * nB, nB, ang, M, op, out, st, log);
+    double *pso = ps_t ? ps_t + (int64_t)i * nB * M * op.ps_len : nullptr;
+    rc = op.precision == 64
+             ? propagate_system<double>(spec, B_mT + (int64_t)i * nB, nB, ang, M, op, out, pso, st, log)
+             : propagate_system<float>(spec, B_mT + (int64_t)i * nB, nB, ang, M, op, out, pso, st, log);
     if (rc) return rc;
     aoff += M * N * 2;
   }

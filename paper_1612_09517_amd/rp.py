@@ -32,7 +32,8 @@ class _System(ctypes.Structure):
 class _Opts(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("init_mode", ctypes.c_int32), ("tol", ctypes.c_double),
                 ("rdt", ctypes.c_double), ("r_scale", ctypes.c_double), ("workspace_bytes", ctypes.c_int64),
-                ("flags", ctypes.c_int32), ("krylov_dim", ctypes.c_int32), ("max_growth", ctypes.c_double)]
+                ("flags", ctypes.c_int32), ("krylov_dim", ctypes.c_int32), ("max_growth", ctypes.c_double),
+                ("ps_t_len", ctypes.c_int64)]
 
 
 _lib = None
@@ -112,10 +113,11 @@ class _CSystem:
 
 
 def _opts(precision=64, init_mode=0, tol=0.0, rdt=0.0, r_scale=0.0, workspace_bytes=0, flags=0, max_growth=0.0,
-          krylov_dim=0):
+          krylov_dim=0, ps_t_len=0):
     o = _Opts()
     o.precision, o.init_mode, o.tol, o.rdt, o.r_scale = precision, init_mode, tol, rdt, r_scale
     o.workspace_bytes, o.flags, o.krylov_dim, o.max_growth = workspace_bytes, flags, krylov_dim, max_growth
+    o.ps_t_len = ps_t_len
     return o
 
 
@@ -155,11 +157,13 @@ def sample(system: SpinSystem, seed, M, first=0, stream_id=0, basis_mode=0, out=
 
 def propagate(systems, B_mT, angles, M, precision=64, init_mode=0, tol=0.0, rdt=0.0, r_scale=0.0,
               workspace_bytes=0, out=None, profile=False, tiled=False, xcd=None, graph=True, max_growth=0.0,
-              arnoldi=False, krylov_dim=0, term_scalar=False):
+              arnoldi=False, krylov_dim=0, term_scalar=False, ps_t_len=0):
     """rp_propagate: single-wavepacket yields [n_sys][nB][M] (float64 CUDA tensor).
 
     ``systems`` is a SpinSystem or a list; ``B_mT`` is [n_sys][nB] (host);
     ``angles`` is the concatenation of the per-system [M][N][2] arrays (CUDA).
+    With ``ps_t_len`` > 0 it returns (yields, singlet populations at the step starts
+    [n_sys][nB][M][ps_t_len], NaN past a field's last step).
     """
     import torch
     if isinstance(systems, SpinSystem):
@@ -180,10 +184,12 @@ def propagate(systems, B_mT, angles, M, precision=64, init_mode=0, tol=0.0, rdt=
         flags |= RP_FLAG_XCD_LOCAL
     elif xcd == "spread":
         flags |= RP_FLAG_XCD_SPREAD
-    o = _opts(precision, init_mode, tol, rdt, r_scale, workspace_bytes, flags, max_growth, krylov_dim)
+    o = _opts(precision, init_mode, tol, rdt, r_scale, workspace_bytes, flags, max_growth, krylov_dim, ps_t_len)
+    ps = torch.empty((len(systems), nB, M, ps_t_len), dtype=torch.float64, device="cuda") if ps_t_len > 0 else None
     _check(lib().rp_propagate(arr, len(cs), B.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), nB, ang, M,
-                              ctypes.byref(o), _dev_ptr(out, torch.float64), None, _stream(torch)))
-    return out
+                              ctypes.byref(o), _dev_ptr(out, torch.float64), _dev_ptr(ps, torch.float64),
+                              _stream(torch)))
+    return (out, ps) if ps is not None else out
 
 
 def combine(mean_a, err_a, mean_b, err_b):

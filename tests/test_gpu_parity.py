@@ -7,7 +7,7 @@ import sys
 import numpy as np
 import pytest
 
-from oracle import philox, stats
+from oracle import coherent, philox, stats, yields
 from paper_1612_09517_amd import rp, workloads
 from paper_1612_09517_amd.workloads import SpinSystem
 
@@ -118,6 +118,38 @@ def test_general_spins_exchange_triplet_dissipation(prec, tiled):
     phi = rp.propagate(s, B, ang, 8, precision=prec, tiled=tiled).cpu().numpy()[0]
     want = gc.oracle_phi(s, B[0], philox.sample_angles(77, 0, 8, 3))
     assert _rel(phi, want) < TOL[prec]
+
+
+@pytest.mark.parametrize("prec", [64, 32])
+def test_singlet_population_trajectory(prec):
+    """ps_t: <psi(t)|P_S|psi(t)> at every step start t_j = j dt of each system and field (dt and
+    n_steps from the planner), against the oracle's propagator, NaN past the last step; two
+    systems of different horizons in one call; the yields equal those of a call without it."""
+    s1 = SpinSystem(2, 1, [1, 2, 1], [0.8, -0.3, 0.5], J_mT=0.4, kS=0.5, kT=2.0, T_us=3.0)
+    s2 = SpinSystem(1, 1, [1, 1], [0.6, -0.9], J_mT=-0.2, kS=1.5, kT=0.3, T_us=1.2)
+    B = np.array([[0.0, 1.7, 4.0], [0.3, 2.2, 6.0]])
+    M = 3
+    _say("trajectory, precision", prec)
+    plans = [[rp.plan_field(s, b, precision=prec) for b in row] for s, row in zip((s1, s2), B)]
+    L = max(p["n_steps"] for row in plans for p in row) + 2
+    ang = torch.cat([rp.sample(s1, 61, M).reshape(-1), rp.sample(s2, 62, M).reshape(-1)])
+    phi, ps = rp.propagate([s1, s2], B, ang, M, precision=prec, ps_t_len=L)
+    ref = rp.propagate([s1, s2], B, ang, M, precision=prec, tiled=True)
+    assert torch.equal(phi, ref)
+    ps = ps.cpu().numpy()
+    tol = 1e-11 if prec == 64 else 2e-6
+    for i, (s, seed) in enumerate(((s1, 61), (s2, 62))):
+        d = gc.dense(s)
+        angs = philox.sample_angles(seed, 0, M, s.N)
+        for b, Bv in enumerate(B[i]):
+            fo = yields.FieldOracle(d, Bv, s.T_us)
+            n, dt = plans[i][b]["n_steps"], plans[i][b]["dt"]
+            assert np.all(np.isnan(ps[i, b, :, n:]))
+            for m in range(M):
+                psi0 = coherent.initial_wavepacket(d, angs[m])
+                for j in sorted({0, 1, n // 2, n - 1}):
+                    assert abs(ps[i, b, m, j] - fo.singlet_probability(psi0, j * dt)) < tol
+            assert np.all(np.abs(ps[i, b, :, 0] - 1.0) < tol)     # P_S(0) = 1 for |S> (Eq. 10)
 
 
 def test_deterministic_trace_by_enumeration():

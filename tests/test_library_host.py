@@ -126,7 +126,11 @@ def test_argument_validation_without_device():
     dp = B.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
     fake = ctypes.c_void_p(16)
     assert L.rp_propagate(ctypes.byref(bad.c), 1, dp, 2, fake, 4, None, fake, None, None) == rp.RP_EINVAL
-    assert L.rp_propagate(ctypes.byref(cs.c), 1, dp, 2, fake, 4, None, fake, fake, None) == rp.RP_ENOTIMPL
+    assert L.rp_propagate(ctypes.byref(cs.c), 1, dp, 2, fake, 4, None, fake, fake, None) == rp.RP_EINVAL   # ps_t_len 0
+    oa = rp._opts(flags=rp.RP_FLAG_ARNOLDI, ps_t_len=4)
+    assert L.rp_propagate(ctypes.byref(cs.c), 1, dp, 2, fake, 4, ctypes.byref(oa), fake, fake, None) == rp.RP_ENOTIMPL
+    on = rp._opts(ps_t_len=-1)
+    assert L.rp_propagate(ctypes.byref(cs.c), 1, dp, 2, fake, 4, ctypes.byref(on), fake, None, None) == rp.RP_EINVAL
     assert L.rp_propagate(ctypes.byref(cs.c), 1, None, 2, fake, 4, None, fake, None, None) == rp.RP_EINVAL
     o = rp._opts(precision=16)
     assert L.rp_propagate(ctypes.byref(cs.c), 1, dp, 2, fake, 4, ctypes.byref(o), fake, None, None) == rp.RP_EINVAL
