@@ -203,7 +203,10 @@ def other_workload(args):
         systems, B, M = w.systems, w.fields_mT, args.samples_per_step
     else:
         raise SystemExit("unknown workload " + name)
-    angs = [rp.sample(s, w.seed + i, M) for i, s in enumerate(systems)]
+    R = max(rp.design_size(s.N, args.sampler) for s in systems)
+    if M % R:
+        raise SystemExit(f"--samples-per-step must be a multiple of the design size {R}")
+    angs = [rp.sample(s, w.seed + i, M, basis_mode=args.sampler) for i, s in enumerate(systems)]
     cat = torch.cat([a.reshape(-1) for a in angs])
     for _ in range(args.warmup):
         rp.propagate(systems, B, cat, M, precision=args.precision)
@@ -220,7 +223,8 @@ def other_workload(args):
                 print(json.dumps({"progress": f"fields {f0 + len(B[0, f0:f0 + group])}/{B.shape[1]}",
                                   "t_s": round(time.perf_counter() - t0, 1)}), flush=True)
         phi = torch.cat(parts, dim=1)
-        mean, err = rp.yield_stats(phi.reshape(-1, M))
+        # sign-flip designs: the group means are the independent units
+        mean, err = rp.yield_stats(rp.group_mean(phi.reshape(-1, M), R) if R > 1 else phi.reshape(-1, M))
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t0) / args.steps
     prof = None
@@ -237,7 +241,7 @@ def other_workload(args):
            "higher_is_better": True, "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
            "ms_per_step": dt * 1e3, "dtype": "f32" if args.precision == 32 else "f64", "data": "synthetic",
            "config": {"workload": w.name, "systems": len(systems), "fields": int(B.shape[1]), "samples": M,
-                      "Z_min": min(Zs), "Z_max": max(Zs)},
+                      "Z_min": min(Zs), "Z_max": max(Zs), "sampler": args.sampler, "design_size": R},
            "phi_mean_first_system": [round(float(x), 6) for x in mean[:B.shape[1]].cpu().numpy()],
            "phi_err_first_system": [round(float(x), 6) for x in err[:B.shape[1]].cpu().numpy()],
            "fields_first_system": [round(float(x), 4) for x in B[0]], "profile": prof}
@@ -528,6 +532,9 @@ def main():
                     help="sampling workload: the sweep system (0, 2.5, 10 mT) or the Sec. IV model (1, 3.5 mT)")
     ap.add_argument("--samplers", default="coherent,jz,antithetic,oa3,oa2",
                     help="sampling workload: comma-separated samplers, the first is the reference")
+    ap.add_argument("--sampler", type=int, default=0, choices=[0, 3, 4, 5],
+                    help="tiny/batched/large/paper workloads: rp_sample mode of the directions (0 plain; "
+                         "3-5 sign-flip designs, errors from group means)")
     ap.add_argument("--design", action="store_true",
                     help="sweep to eps <= 1e-3 with sign-flip design sampling (FP32) against plain FP64")
     ap.add_argument("--design-mode", type=int, default=5, choices=[3, 4, 5], help="rp_sample design mode")
