@@ -623,36 +623,56 @@ __global__ __launch_bounds__(kPairThreads) void k_cheb_pair(TermArgs<float> ta, 
   // Higher spins: digits uniform over the workgroup (strides are multiples of 256); a missing
   // partner gets coefficient 0 and reads this thread's own pair.
   int64_t rem = (bx * kBlock) >> nh;
-  for (int k = nh; k < sa.N; ++k) {
-    const int dk = sa.d[k];
-    const int64_t q = rem / dk;
-    const int n = __builtin_amdgcn_readfirstlane((int)(rem - q * dk));
-    rem = q;
-    const int64_t st = sa.stride[k];
-    const bool r1 = sa.rad[k] == 0;
-    const float mk = 0.5f * (float)(dk - 1) - (float)n;
-    const float am = sa.a[k] * mk;
-    A.h1 += r1 ? am : 0.0f;
-    A.h2 += r1 ? 0.0f : am;
-    B.h1 += r1 ? am : 0.0f;
-    B.h2 += r1 ? 0.0f : am;
-    const int64_t Pm = n > 0 ? M - st : M, Pp = n < dk - 1 ? M + st : M;
-    const float fm = n > 0 ? sa.f[k][n - 1] : 0.0f;
-    const float fpl = n < dk - 1 ? sa.f[k][n] : 0.0f;
-    // minus partner (digit n-1) feeds the alpha components from beta ones; plus partner
-    // (digit n+1) feeds beta components from alpha ones
-    const f4 pm0 = ld4<false>(X + (r1 ? 2 : 1) * Z + Pm), pm1 = ld4<false>(X + 3 * Z + Pm);
-    const f4 pp0 = ld4<false>(X + Pp), pp1 = ld4<false>(X + (r1 ? 1 : 2) * Z + Pp);
-    A.y0 = cadd(A.y0, cscale(fm, lo(pm0)));
-    B.y0 = cadd(B.y0, cscale(fm, hi(pm0)));
-    A.y3 = cadd(A.y3, cscale(fpl, lo(pp1)));
-    B.y3 = cadd(B.y3, cscale(fpl, hi(pp1)));
-    const cx<float> ua = cscale(fm, lo(pm1)), ub = cscale(fm, hi(pm1));
-    const cx<float> va = cscale(fpl, lo(pp0)), vb = cscale(fpl, hi(pp0));
-    A.y1 = cadd(A.y1, r1 ? ua : va);
-    A.y2 = cadd(A.y2, r1 ? va : ua);
-    B.y1 = cadd(B.y1, r1 ? ub : vb);
-    B.y2 = cadd(B.y2, r1 ? vb : ub);
+  for (int k0 = nh; k0 < sa.N; k0 += 2) {   // two nuclei per batch: eight 16-byte loads in flight
+    f4 pm0[2], pm1[2], pp0[2], pp1[2];
+    float fm[2], fpl[2];
+    bool r1v[2];
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const int k = k0 + j;
+      fm[j] = 0.0f;
+      fpl[j] = 0.0f;
+      r1v[j] = true;
+      if (k < sa.N) {
+        const int dk = sa.d[k];
+        const int64_t q = rem / dk;
+        const int n = __builtin_amdgcn_readfirstlane((int)(rem - q * dk));
+        rem = q;
+        const int64_t st = sa.stride[k];
+        const bool r1 = sa.rad[k] == 0;
+        r1v[j] = r1;
+        const float am = sa.a[k] * (0.5f * (float)(dk - 1) - (float)n);
+        A.h1 += r1 ? am : 0.0f;
+        A.h2 += r1 ? 0.0f : am;
+        B.h1 += r1 ? am : 0.0f;
+        B.h2 += r1 ? 0.0f : am;
+        const int64_t Pm = n > 0 ? M - st : M, Pp = n < dk - 1 ? M + st : M;
+        fm[j] = n > 0 ? sa.f[k][n - 1] : 0.0f;
+        fpl[j] = n < dk - 1 ? sa.f[k][n] : 0.0f;
+        // minus partner (digit n-1) feeds the alpha components from beta ones; plus partner
+        // (digit n+1) feeds beta components from alpha ones
+        pm0[j] = ld4<false>(X + (r1 ? 2 : 1) * Z + Pm);
+        pm1[j] = ld4<false>(X + 3 * Z + Pm);
+        pp0[j] = ld4<false>(X + Pp);
+        pp1[j] = ld4<false>(X + (r1 ? 1 : 2) * Z + Pp);
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      if (k0 + j < sa.N) {
+        const bool r1 = r1v[j];
+        A.y0 = cadd(A.y0, cscale(fm[j], lo(pm0[j])));
+        B.y0 = cadd(B.y0, cscale(fm[j], hi(pm0[j])));
+        A.y3 = cadd(A.y3, cscale(fpl[j], lo(pp1[j])));
+        B.y3 = cadd(B.y3, cscale(fpl[j], hi(pp1[j])));
+        const cx<float> ua = cscale(fm[j], lo(pm1[j])), ub = cscale(fm[j], hi(pm1[j]));
+        const cx<float> va = cscale(fpl[j], lo(pp0[j])), vb = cscale(fpl[j], hi(pp0[j]));
+        A.y1 = cadd(A.y1, r1 ? ua : va);
+        A.y2 = cadd(A.y2, r1 ? va : ua);
+        B.y1 = cadd(B.y1, r1 ? ub : vb);
+        B.y2 = cadd(B.y2, r1 ? vb : ub);
+      }
+    }
   }
   // phi_{n+1}, its singlet amplitude and the accumulator, two indices per 16-byte access
   cx<float> za[4], zb[4];
