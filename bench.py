@@ -580,9 +580,8 @@ def main():
         print(json.dumps({"copy_probe_bytes_each_way": 4 * n, "copies": 3}), flush=True)
         return
     if args.gpus != 1:
-        print(json.dumps({"error": "this benchmark runs on one GPU only; multi-GPU runs are not part of "
-                                   "this build (the sweep would shard jobs across GPUs with one final "
-                                   "all-reduce of per-field sums)"}))
+        print(json.dumps({"error": "bench.py measures one GPU only (--gpus 1); a multi-GPU sweep would "
+                                   "shard jobs across GPUs with one final all-reduce of per-field sums"}))
         sys.exit(2)
 
     import torch

@@ -178,3 +178,12 @@ def test_design_size_matches_oracle_design():
     assert rp.lib().rp_design_size(-1, 4) == rp.RP_EINVAL
     with pytest.raises(rp.RpError):
         rp.design_size(3, 9)
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """bench.py --gpus N > 1 stops with a message before touching a GPU."""
+    import subprocess
+    import sys
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2 and "one GPU only" in r.stdout
