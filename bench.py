@@ -35,8 +35,8 @@ def cpu_baseline(w, seconds_target=20.0):
     t0 = time.perf_counter()
     large.yield_augmented(sp, B, s.T_us * frac, psi, tau=1.0)
     dt = time.perf_counter() - t0
-    if dt < seconds_target / 4:
-        frac = min(1.0, frac * seconds_target / max(dt, 1e-3) / 2)
+    if dt < seconds_target / 2:   # a probe shorter than 10 s: time a longer stretch of the horizon
+        frac = min(1.0, frac * 0.75 * seconds_target / max(dt, 1e-3))
         t0 = time.perf_counter()
         large.yield_augmented(sp, B, s.T_us * frac, psi, tau=1.0)
         dt = time.perf_counter() - t0
