@@ -124,7 +124,8 @@ def test_general_spins_exchange_triplet_dissipation(prec, tiled):
 def test_singlet_population_trajectory(prec):
     """ps_t: <psi(t)|P_S|psi(t)> at every step start t_j = j dt of each system and field (dt and
     n_steps from the planner), against the oracle's propagator, NaN past the last step; two
-    systems of different horizons in one call; the yields equal those of a call without it."""
+    systems of different horizons in one call; the yields equal those of a call without it;
+    a workspace of a few wavepackets (several chunks) gives the same trajectories."""
     s1 = SpinSystem(2, 1, [1, 2, 1], [0.8, -0.3, 0.5], J_mT=0.4, kS=0.5, kT=2.0, T_us=3.0)
     s2 = SpinSystem(1, 1, [1, 1], [0.6, -0.9], J_mT=-0.2, kS=1.5, kT=0.3, T_us=1.2)
     B = np.array([[0.0, 1.7, 4.0], [0.3, 2.2, 6.0]])
@@ -136,7 +137,10 @@ def test_singlet_population_trajectory(prec):
     phi, ps = rp.propagate([s1, s2], B, ang, M, precision=prec, ps_t_len=L)
     ref = rp.propagate([s1, s2], B, ang, M, precision=prec, tiled=True)
     assert torch.equal(phi, ref)
+    # several chunks per system (the workspace holds a few wavepackets): same trajectories
+    phi_c, ps_c = rp.propagate([s1, s2], B, ang, M, precision=prec, ps_t_len=L, workspace_bytes=80000)
     ps = ps.cpu().numpy()
+    assert torch.equal(phi_c, phi) and np.array_equal(ps_c.cpu().numpy(), ps, equal_nan=True)
     tol = 1e-11 if prec == 64 else 2e-6
     for i, (s, seed) in enumerate(((s1, 61), (s2, 62))):
         d = gc.dense(s)
