@@ -509,6 +509,8 @@ def main():
     ap.add_argument("--workspace-gb", type=float, default=0.0,
                     help="device workspace cap per call (bounds how many wavepackets run together)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp64-probe", action="store_true",
+                    help="skip the untimed plain-FP64 rate probe of the default bench line")
     ap.add_argument("--copy-probe", type=float, default=0.0,
                     help="only copy a buffer of this many GiB three times (calibrates HBM counters)")
     ap.add_argument("--workload", default="sweep",
@@ -630,6 +632,18 @@ def main():
     M_needed = np.ceil((sig / 1e-3) ** 2)
     sweep_props = float(M_needed.max()) * B.shape[1]
     achieved = prof["elements"] * bpe / (prof["term_ms"] * 1e-3) / 1e9
+    plain64 = None
+    if args.precision == 32 and not args.no_fp64_probe:
+        # untimed: the plain FP64 rate on the same fields, for the sweep wall time it implies
+        M64 = 2
+        ang64 = rp.sample(s, w.seed, M64, first=10 ** 6)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        rp.propagate(s, B, ang64, M64, precision=64)
+        torch.cuda.synchronize()
+        rate64 = M64 * B.shape[1] / (time.perf_counter() - t1)
+        plain64 = {"propagations_per_s": rate64, "sweep_wall_s_at_eps_1e-3": sweep_props / rate64,
+                   "sample": f"{M64} samples x {B.shape[1]} fields, complex FP64, one call"}
     rec = {
         "metric": "sweep wall time at sigma(Phi_S)<=1e-3 vs plain FP64 MC; H.psi HBM GB/s vs peak",
         "value": value,
@@ -663,6 +677,7 @@ def main():
                      "quad_time_frac": prof["quad_ms"] / max(prof["total_ms"], 1e-9)},
         "sigma_max": float(sig.max()),
         "sweep_wall_s_at_eps_1e-3": sweep_props / value,
+        "plain_fp64": plain64,
     }
     if not args.no_cpu_baseline:
         rec["cpu_baseline"] = cpu_baseline(w)
