@@ -62,6 +62,13 @@ def test_design_sampler_bit_exact(mode):
     got = rp.sample(s, seed=99, M=45, first=7, stream_id=1, basis_mode=mode).cpu().numpy()
     want = philox.sample_design(99, 7, 45, s.N, mode, stream=1)
     assert np.array_equal(got, want)
+    # the Sec. IV model's 20 nuclei: Hadamard order 32 (64 rows for mode 4), a ragged window
+    # spanning three groups
+    p = workloads.paper_model().systems[0]
+    R20 = rp.design_size(p.N, mode)
+    assert R20 == {3: 2, 4: 64, 5: 32}[mode]
+    got = rp.sample(p, seed=5, M=2 * R20 + 3, first=R20 - 2, basis_mode=mode).cpu().numpy()
+    assert np.array_equal(got, philox.sample_design(5, R20 - 2, 2 * R20 + 3, p.N, mode))
 
 
 def test_design_group_means_recover_trace():
