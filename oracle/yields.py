@@ -23,6 +23,7 @@ import numpy as np
 import scipy.linalg as sla
 
 from .coherent import initial_wavepacket
+from .spin import spin_ops
 
 
 def integrated_operator(G, A, T):
@@ -73,6 +74,56 @@ class FieldOracle:
     def trace_yield(self):
         """Deterministic Phi_S(T) = (k_S/Z) Tr[P_S X_T] (Eq. 14 and 20)."""
         return float(self.sys.kS * np.real(np.trace(self.sys.PS @ self.X)) / self.sys.Z)
+
+    def singlet_block(self):
+        """A = <S|X_T|S>, the nuclear-space operator with phi_S(Omega) = k_S <Omega|A|Omega>
+        (the electron part of every wavepacket of Eq. 19 is the singlet)."""
+        Z = self.sys.Z
+        X4 = self.X.reshape(4, Z, 4, Z)
+        s = self.sys.singlet.astype(complex)
+        return np.einsum("e,eifj,f->ij", s.conj(), X4, s)
+
+    def second_moment(self):
+        """E_Omega[phi_S^2] over directions uniform on every sphere (Eq. 18), exactly.
+
+        phi_S^2 = k_S^2 <Omega,Omega| A (x) A |Omega,Omega>, and the directions of distinct
+        nuclei are independent, so the mean factorises over nuclei into the second moment
+        E[|Omega_k><Omega_k| (x) |Omega_k><Omega_k|] of one coherent state.  |Omega>(x)|Omega>
+        is the coherent state of spin 2I in I (x) I, and averaging it over the sphere gives,
+        by rotation invariance and irreducibility (Schur's lemma), the projector onto the
+        spin-2I subspace divided by its dimension 4I + 1.  For spin 1/2 this is
+        (1 + SWAP) / 6, the symmetric-subspace (unitary 2-design) moment.
+        """
+        N = len(self.sys.two_I)
+        kS = self.sys.kS
+        if N == 0:
+            return float((kS * np.real(self.singlet_block()[0, 0])) ** 2)
+        dims = [t + 1 for t in self.sys.two_I]
+        A = self.singlet_block().reshape(dims + dims)
+        Qs = []
+        for t in self.sys.two_I:
+            d = t + 1
+            ops = spin_ops(t)[:3]
+            J2 = sum(np.kron(o, np.eye(d)) @ np.kron(o, np.eye(d)) + 2 * np.kron(o, o)
+                     + np.kron(np.eye(d), o) @ np.kron(np.eye(d), o) for o in ops)
+            w, V = np.linalg.eigh(J2)
+            top = t * (t + 1)                        # J(J+1) with J = 2I = t
+            sel = np.abs(w - top) < 1e-8
+            assert sel.sum() == 2 * t + 1
+            P = V[:, sel] @ V[:, sel].conj().T
+            Qs.append((P / (2 * t + 1)).reshape(d, d, d, d))   # [(b, b'), (a, a')]
+        letters = iter("abcdefghijklmnopqrstuvwxyzABCDEFGHIJKLMNOPQRSTUVWXYZ")
+        i = [next(letters) for _ in range(N)]
+        j = [next(letters) for _ in range(N)]
+        ip = [next(letters) for _ in range(N)]
+        jp = [next(letters) for _ in range(N)]
+        terms = ["".join(i + j), "".join(ip + jp)] + [j[k] + jp[k] + i[k] + ip[k] for k in range(N)]
+        val = np.einsum(",".join(terms) + "->", A, A, *Qs, optimize="greedy")
+        return float(kS * kS * np.real(val))
+
+    def sample_sigma(self):
+        """Exact standard deviation of one sample's yield: sqrt(E[phi^2] - Phi_S(T)^2)."""
+        return float(np.sqrt(max(0.0, self.second_moment() - self.trace_yield() ** 2)))
 
     def survival(self, psi0, t):
         """Population N(t) = ||exp(-iGt) psi0||^2."""

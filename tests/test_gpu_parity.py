@@ -177,6 +177,38 @@ def test_deterministic_trace_by_enumeration():
         assert abs(phi[b].mean() - gc.oracle_trace(s, Bv)) < 1e-10
 
 
+@pytest.mark.parametrize("prec", [64, 32])
+def test_monte_carlo_within_3_sigma_of_trace(prec):
+    """Stochastic against deterministic trace (Eq. 18 against Eq. 14) with the exact sigma: the
+    tiny workload's plain Monte Carlo mean (M = 64 seeded samples, all 16 fields, rp_yield on
+    the GPU) lies within 3 sigma / sqrt(M) of the oracle trace at every field, where sigma is
+    the exact single-sample deviation from the oracle's coherent-state second moment; the
+    GPU's estimated error agrees with sigma / sqrt(M) within the chi-square spread; and at
+    1 mT a long run (M = 8192) is within 3 sigma / sqrt(M) with its sample deviation within 5 %
+    of the exact 9.7054e-3."""
+    w = workloads.tiny_c1()
+    s = w.systems[0]
+    d = gc.dense(s)
+    _say("Monte Carlo against the trace, 3 sigma exact, precision", prec)
+    ang = rp.sample(s, w.seed, w.M)
+    phi = rp.propagate(s, w.fields_mT, ang, w.M, precision=prec)[0]
+    mean, err = (x.cpu().numpy() for x in rp.yield_stats(phi))
+    for b, Bv in enumerate(w.fields_mT[0]):
+        fo = yields.FieldOracle(d, Bv, s.T_us)
+        tr, sig = fo.trace_yield(), fo.sample_sigma()
+        assert abs(mean[b] - tr) < 3 * sig / math.sqrt(w.M), (Bv, mean[b], tr, sig)
+        assert abs(err[b] * math.sqrt(w.M) / sig - 1) < 4 / math.sqrt(2 * (w.M - 1)), (Bv, err[b], sig)
+    M = 8192
+    ang = rp.sample(s, w.seed, M, first=10 ** 5)
+    phi = rp.propagate(s, np.array([[1.0]]), ang, M, precision=prec)[0]
+    mean, err = (x.cpu().numpy()[0] for x in rp.yield_stats(phi))
+    fo = yields.FieldOracle(d, 1.0, s.T_us)
+    sig = fo.sample_sigma()
+    assert abs(sig - 9.7054e-3) < 5e-8
+    assert abs(mean - fo.trace_yield()) < 3 * sig / math.sqrt(M)
+    assert abs(err * math.sqrt(M) / sig - 1) < 0.05
+
+
 def test_no_nuclei_closed_form():
     s = SpinSystem(0, 0, [], [], J_mT=0.9, kS=1.3, kT=0.2, T_us=2.5)
     _say("no nuclei")
@@ -196,7 +228,7 @@ def test_multi_block_ragged_mixed_radix():
     want = gc.oracle_phi_sparse(s, B[0], philox.sample_angles(9, 0, 3, s.N))
     for prec in (64, 32):
         phi = rp.propagate(s, B, ang, 3, precision=prec).cpu().numpy()[0]
-        assert _rel(phi, want) < TOL[prec] * (10 if prec == 64 else 1)
+        assert _rel(phi, want) < TOL[prec], _rel(phi, want)
 
 
 def test_reordered_axes_spin1_first():
@@ -211,7 +243,7 @@ def test_reordered_axes_spin1_first():
     want = gc.oracle_phi_sparse(s, B[0], philox.sample_angles(12, 0, 3, s.N))
     for prec in (64, 32):
         phi = rp.propagate(s, B, ang, 3, precision=prec).cpu().numpy()[0]
-        assert _rel(phi, want) < TOL[prec] * (10 if prec == 64 else 1)
+        assert _rel(phi, want) < TOL[prec], _rel(phi, want)
 
 
 def test_pair_term_kernel_matches_scalar_term_kernel():
@@ -433,9 +465,10 @@ def test_arnoldi_propagator_matches_oracle(krylov):
         ang = rp.sample(s, 60 + i, 3)
         a_h = philox.sample_angles(60 + i, 0, 3, s.N)
         want = gc.oracle_phi_sparse(s, B[0], a_h) if sparse else gc.oracle_phi(s, B[0], a_h)
-        for prec, tol in ((64, 1e-9), (32, 1e-5)):
+        for prec, tol in ((64, 1e-10), (32, 1e-5)):
             _say(f"arnoldi case {i} precision {prec} krylov {krylov}")
             phi = rp.propagate(s, B, ang, 3, precision=prec, arnoldi=True, krylov_dim=krylov).cpu().numpy()[0]
+            _say("  max relative error", _rel(phi, want))
             assert _rel(phi, want) < tol, (i, prec, krylov, _rel(phi, want))
 
 

@@ -437,3 +437,162 @@ def test_stats_eq23():
     m, e = stats.mc_mean_error(phi)
     assert abs(m[0] - 0.3) < 1e-15
     assert abs(e[0] - np.sqrt(((phi - 0.3) ** 2).sum() / 3) / 2) < 1e-15
+
+
+# --------------------------------------------------------------------------- pins added for the statistics and trajectories
+def _one_nucleus_ps(t, B, a_mT, k):
+    """Trace-averaged singlet probability P_S(t) = e^{-kt} p(t) for one spin-1/2 nucleus on
+    radical 1, J = 0, kS = kT = k: the time-domain form of the closed-form yield above, whose
+    L(nu) = k int e^{-kt} cos(nu t) dt is the Laplace transform of each cosine."""
+    w, a = G * B, G * a_mT
+    Om = math.hypot(w, a)
+    c2, s2 = (1 + w / Om) / 2, (1 - w / Om) / 2
+    C = lambda nu: math.cos(nu * t)
+    p = (0.25 + 0.25 * ((0.5 + w * w / (2 * Om * Om)) + a * a / (2 * Om * Om) * C(Om))
+         + 0.25 * (s2 * (C((Om + w - a) / 2) + C((Om + w + a) / 2))
+                   + c2 * (C((Om - w + a) / 2) + C((Om - w - a) / 2))))
+    return math.exp(-k * t) * p
+
+
+@pytest.mark.parametrize("B", [0.0, 0.7, 3.0])
+def test_singlet_probability_one_nucleus_closed_form(B):
+    """FieldOracle.singlet_probability at t > 0: the mean over the two basis states of the nucleus
+    (theta = 0, pi; Eq. 14 with Z = 2) is the closed-form e^{-kt} p(t).  A wrong sign in the
+    exponent, P_T in place of P_S or a missing decay would all fail here."""
+    s = spin.DenseSystem((1, 0), [1], [0.5], kS=1.3, kT=1.3)
+    fo = yields.FieldOracle(s, B, 4.0)
+    for t in (0.0, 0.013, 0.2, 1.1, 3.7):
+        got = np.mean([fo.singlet_probability(coherent.initial_wavepacket(s, [[c, 0.4]]), t) for c in (1.0, -1.0)])
+        assert abs(got - _one_nucleus_ps(t, B, 0.5, 1.3)) < 1e-13, (t, got)
+
+
+def test_singlet_probability_integrates_to_phi():
+    """k_S times a composite Gauss-Legendre integral of FieldOracle.singlet_probability over
+    [0, T] equals FieldOracle.phi (Van Loan route) for unequal rates, exchange and a spin-1
+    nucleus: the trajectory and the integrated operator are two independent routes to Eq. 22."""
+    s = spin.DenseSystem((1, 1), [2, 1], [0.6, -0.4], J_mT=0.3, kS=2.0, kT=0.5)
+    B, T = 1.1, 1.5
+    fo = yields.FieldOracle(s, B, T)
+    psi = coherent.initial_wavepacket(s, philox.sample_angles(41, 0, 1, 2)[0])
+    x, w = np.polynomial.legendre.leggauss(16)
+    npan = 60
+    h = T / npan
+    tot = sum(0.5 * h * wi * fo.singlet_probability(psi, p * h + 0.5 * h * (xi + 1))
+              for p in range(npan) for xi, wi in zip(x, w))
+    assert abs(s.kS * tot - fo.phi(psi)) < 1e-12
+
+
+def test_mc_mean_error_closed_form_and_reductions():
+    """Eq. 23 on constructed samples: the control-variate estimate mean(phi - beta (g - mu)) and
+    its error sqrt(s'^2/M + (beta err_mu)^2), written out by hand; beta = 0 reduces to the plain
+    estimate; a perfectly correlated control variate leaves only mu's error."""
+    phi = np.array([1.0, 2.0, 3.0, 4.0])
+    g = np.array([1.0, 0.0, 0.0, 0.0])
+    # phi - 2 (g - 0.5) = [0, 3, 4, 5]: mean 3, s^2 = (9 + 0 + 1 + 4) / 3
+    m, e = stats.cv_mean_error(phi[None], g[None], [0.5], [2.0])
+    assert abs(m[0] - 3.0) < 1e-15 and abs(e[0] - math.sqrt(14.0 / 3.0) / 2.0) < 1e-15
+    m, e = stats.cv_mean_error(phi[None], g[None], [0.5], [2.0], mu_err=[0.1])
+    assert abs(m[0] - 3.0) < 1e-15 and abs(e[0] - math.sqrt(14.0 / 12.0 + 0.04)) < 1e-15
+    m0, e0 = stats.cv_mean_error(phi[None], g[None], [0.7], [0.0], mu_err=[5.0])
+    mp, ep = stats.mc_mean_error(phi[None])
+    assert m0[0] == mp[0] and e0[0] == ep[0]
+    rng = np.random.default_rng(4)
+    gg = rng.normal(size=50)
+    m, e = stats.cv_mean_error((0.3 + 1.7 * gg)[None], gg[None], [0.25], [1.7], mu_err=[0.02])
+    assert abs(m[0] - (0.3 + 1.7 * 0.25)) < 1e-14 and abs(e[0] - 1.7 * 0.02) < 1e-14
+
+
+def test_cv_estimate_unbiased_and_error_calibrated():
+    """With beta and mu fixed independently of the samples, the control-variate mean is unbiased
+    and its stated error matches the spread of repeated estimates (synthetic phi = 0.4 + g + noise,
+    E[g] = 0 known exactly)."""
+    rng = np.random.default_rng(11)
+    R, M = 4000, 40
+    g = rng.uniform(-1, 1, (R, M))
+    phi = 0.4 + g + 0.1 * rng.normal(size=(R, M))
+    m, e = stats.cv_mean_error(phi, g, np.zeros(R), np.full(R, 0.9))
+    assert abs(m.mean() - 0.4) < 4 * m.std() / math.sqrt(R)
+    assert abs(m.std() / np.sqrt(np.mean(e ** 2)) - 1.0) < 0.05
+
+
+def test_basis_digits_follow_the_coherent_sampler_and_are_uniform():
+    """Random J_z eigenstates: digit n_k = floor(u1 (2I+1)) where u1 = (cos theta + 1) / 2 of the
+    pinned coherent-state sampler (same Philox block); the digits are uniform on 0..2I and
+    independent across nuclei (chi-square over pairs)."""
+    two_I = [1, 2, 4, 3]
+    M = 6000
+    dig = philox.sample_basis_digits(91, 5, M, two_I)[:, :, 0].astype(int)
+    ang = philox.sample_angles(91, 5, M, len(two_I))
+    u1 = (ang[:, :, 0] + 1.0) / 2.0
+    for k, t in enumerate(two_I):
+        assert np.array_equal(dig[:, k], np.floor(u1[:, k] * (t + 1)).astype(int))
+        cnt = np.bincount(dig[:, k], minlength=t + 1)
+        assert len(cnt) == t + 1
+        p = 1.0 / (t + 1)
+        assert np.all(np.abs(cnt / M - p) < 4 * math.sqrt(p * (1 - p) / M))
+    joint = np.zeros((3, 5))
+    for a, b in zip(dig[:, 1], dig[:, 2]):
+        joint[a, b] += 1
+    chi2 = ((joint - M / 15.0) ** 2 / (M / 15.0)).sum()
+    assert chi2 < 40.0                       # 14 degrees of freedom: P(chi2 > 40) < 3e-4
+
+
+# Config-1 values (Z = 8: nuclei 0.8, 0.3 mT on radical 1 and 0.5 mT on radical 2, J = 0,
+# kS = kT = 1 /us, gamma = 176.085963023) from an independent dense FP64 computation made
+# before this oracle was written; not printed in the paper.
+_C1_PHI_T10 = {0.0: 0.426504771064632, 0.5: 0.365141595063740, 1.0: 0.425442014488798,
+               2.0: 0.474744847099402, 5.0: 0.502010522115456}
+_C1_PHI_INF = {0.0: 0.426523955195249, 0.5: 0.365158138995509, 1.0: 0.425461389047915,
+               2.0: 0.474766206199866, 5.0: 0.502031923513515}
+
+
+@pytest.mark.parametrize("B", sorted(_C1_PHI_T10))
+def test_config1_trace_against_independent_values(B):
+    w = workloads.tiny_c1()
+    sysd = w.systems[0]
+    s = spin.DenseSystem((sysd.n1, sysd.n2), sysd.two_I, sysd.a_mT, kS=sysd.kS, kT=sysd.kT)
+    assert abs(yields.FieldOracle(s, B, 10.0).trace_yield() - _C1_PHI_T10[B]) < 1e-13
+    assert abs(yields.FieldOracle(s, B, 60.0).trace_yield() - _C1_PHI_INF[B]) < 1e-13
+
+
+def test_config1_exact_sample_sigma():
+    """The exact single-sample deviation at 1 mT, T = 10 us, from the coherent-state second moment:
+    9.7054e-3 in the same independent computation; a 20,000-sample Monte Carlo gives 0.009695."""
+    w = workloads.tiny_c1()
+    sysd = w.systems[0]
+    s = spin.DenseSystem((sysd.n1, sysd.n2), sysd.two_I, sysd.a_mT, kS=sysd.kS, kT=sysd.kT)
+    assert abs(yields.FieldOracle(s, 1.0, 10.0).sample_sigma() - 9.7054e-3) < 5e-8
+
+
+def _product_rule(two_I, degree):
+    """Product quadrature over the spheres, exact for polynomials of the given degree in each n_k."""
+    rules = []
+    for t in two_I:
+        x, w = np.polynomial.legendre.leggauss(degree * t // 2 + 1 + degree // 2)
+        nphi = degree * t + 1
+        rules.append([(xi, 2 * np.pi * j / nphi, wi / 2 / nphi) for xi, wi in zip(x, w) for j in range(nphi)])
+    return rules
+
+
+@pytest.mark.parametrize("case", ["half", "spin1"])
+def test_second_moment_equals_sphere_quadrature(case):
+    """E[phi_S^2] (coherent-state second moment, spin-2I projector) against a product quadrature
+    over the spheres exact for phi_S^2, whose degree in n_k is twice that of phi_S (2I): all
+    spin-1/2 with unequal rates and exchange, and with a spin-1 nucleus (where the full
+    symmetric-subspace moment (1 + SWAP)/(d(d+1)) would be wrong)."""
+    if case == "half":
+        s = spin.DenseSystem((2, 1), [1, 1, 1], [0.8, -0.3, 0.5], J_mT=0.4, kS=2.0, kT=0.5)
+        fo = yields.FieldOracle(s, 1.2, 3.0)
+    else:
+        s = spin.DenseSystem((1, 1), [2, 1], [0.6, -0.4], J_mT=0.2, kS=1.5, kT=0.5)
+        fo = yields.FieldOracle(s, 0.8, 3.0)
+    m1 = m2 = 0.0
+    for combo in itertools.product(*_product_rule(s.two_I, 2)):
+        ang = np.array([[c[0], c[1]] for c in combo])
+        wt = np.prod([c[2] for c in combo])
+        p = fo.phi(coherent.initial_wavepacket(s, ang))
+        m1 += wt * p
+        m2 += wt * p * p
+    assert abs(m1 - fo.trace_yield()) < 1e-13
+    assert abs(m2 - fo.second_moment()) < 1e-13
+    assert fo.sample_sigma() > 1e-4
