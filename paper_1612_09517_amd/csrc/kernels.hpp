@@ -75,6 +75,19 @@ struct FieldDev {
   R s1, s2;       // 1/r and 2/r
 };
 
+// One job (system, field, sample) of a chunk in the job queue of the tiled kernels.  The jobs of a
+// chunk are laid out one after another: wavepacket vectors at `vec` (4Z complex numbers),
+// singlet amplitudes at `amp` within each term slab (Z), workgroups (256-index tiles) from `blk`.
+struct QJob {
+  int32_t sys;             // index into the per-call system table
+  int32_t field;           // index into the per-call field tables (system-major)
+  int32_t nbx;             // tiles of this job
+  int32_t pad;
+  int64_t Z;               // nuclear states
+  int64_t vec, amp, blk;   // offsets within the chunk (complex numbers, complex numbers, tiles)
+  int64_t tab;             // row of the job's first nucleus in the coherent-state table
+};
+
 template <typename R>
 struct TermArgs {
   const cx<R> *phin;       // phi_n, [jobs][4Z]
@@ -85,8 +98,13 @@ struct TermArgs {
   const FieldDev<R> *fields;
   const cx<R> *coef;       // [fields][n_terms]
   const int32_t *job_field;
-  double *part_norm;       // first term only: [jobs][nbx]
-  int64_t nbx;
+  double *part_norm;       // first term only: [tiles]
+  // Job queue (several systems in one launch): tile -> job, job descriptors, system table.
+  const int32_t *tile_job;
+  const QJob *jobs;
+  const SysArgs<R> *systab;
+  int64_t nbx;             // tiles per job when every job of the launch has the same system
+  int64_t tiles;           // tiles of the launch
   int32_t njobs;
   int32_t n;               // producing phi_{n+1}
   int32_t n_terms;
@@ -96,12 +114,15 @@ struct TermArgs {
 template <typename R>
 struct QuadArgs {
   const cx<R> *d;          // [n_terms][slab]
-  int64_t slab;            // elements per term slab (jobs_in_chunk * Z)
+  int64_t slab;            // elements per term slab (sum of Z over the chunk's jobs)
   const R *ell;            // [fields][n_terms][rank_pad]
   const int32_t *job_field;
-  double *part;            // [jobs][nbx][2]: quadratic form, |d_0|^2/2
+  double *part;            // [tiles][2]: quadratic form, |d_0|^2/2
+  const int32_t *tile_job; // job queue (several systems): as in TermArgs
+  const QJob *jobs;
   int64_t Z;
   int64_t nbx;
+  int64_t tiles;
   int32_t njobs;
   int32_t n_terms;
   int32_t rank_pad;
@@ -109,14 +130,16 @@ struct QuadArgs {
 };
 
 struct FinArgs {
-  const double *part_q;    // [jobs][nbx][2]
-  const double *part_norm; // [jobs][nbx]
+  const double *part_q;    // [tiles][2]
+  const double *part_norm; // [tiles]
   double *phi;             // [jobs] accumulated yields of this chunk
   double *prev_norm;       // [jobs]
   int *flag;
   const int32_t *job_field;
   const double *dt;        // [fields]
   int32_t *stepc;          // [jobs] steps finalised so far (read, then incremented)
+  const QJob *jobs;        // job queue (several systems), or null: nbx tiles per job
+  const double *sys_k;     // job queue: [systems][2] = (kS, k_min)
   int64_t nbx;
   int32_t njobs;
   int32_t pad;

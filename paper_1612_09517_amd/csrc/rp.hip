@@ -69,6 +69,38 @@ __device__ __forceinline__ double block_sum(double v, double *lds) {
   return t;
 }
 
+// The tile a workgroup of a tiled launch works on.  In a launch over the jobs of one system
+// every job has nbx tiles and job = L / nbx; in the job queue (several systems, unequal Z)
+// tile_job maps the tile to its job, whose descriptor holds the job's offsets.  The tile index
+// L is also the index of the workgroup's partial sums.
+struct TileRef {
+  int64_t job, bx, Z, vec, amp;
+  int32_t sys, fi;
+};
+template <bool Q, typename A>
+__device__ __forceinline__ TileRef tile_ref(const A &ta, int64_t L, int64_t Z1) {
+  TileRef t;
+  if constexpr (Q) {
+    t.job = __builtin_amdgcn_readfirstlane(ta.tile_job[L]);
+    const QJob &j = ta.jobs[t.job];
+    t.sys = j.sys;
+    t.fi = j.field;
+    t.Z = j.Z;
+    t.vec = j.vec;
+    t.amp = j.amp;
+    t.bx = L - j.blk;
+  } else {
+    t.job = L / ta.nbx;
+    t.bx = L - t.job * ta.nbx;
+    t.Z = Z1;
+    t.vec = t.job * Z1 * 4;
+    t.amp = t.job * Z1;
+    t.sys = 0;
+    t.fi = ta.job_field[t.job];
+  }
+  return t;
+}
+
 // ----------------------------------------------------------------------------- sampler (Eq. 18)
 struct SampleArgs {
   double *angles;
@@ -201,8 +233,12 @@ struct InitArgs {
   cx<R> *psi;                   // [jobs][4Z]
   const cx<double> *tab;        // [M][N][5]
   const int32_t *job_sample;    // [jobs]
+  const int32_t *tile_job;      // job queue (several systems): tile -> job
+  const QJob *jobs;             // job queue: descriptors (offsets, coherent-table row)
+  const SysArgs<R> *systab;     // job queue: systems
   int64_t Z;
   int64_t nbx;
+  int64_t tiles;
   int32_t njobs, N;
   int32_t stride[RP_MAX_NUCLEI];
   int32_t d[RP_MAX_NUCLEI];
@@ -210,25 +246,46 @@ struct InitArgs {
 };
 
 // psi_0 = |S> (x) prod_k |Omega_k>, |S> = (|ab> - |ba>)/sqrt 2 (Eq. 10, 18-19).
-template <typename R>
+template <typename R, bool Q>
 __global__ __launch_bounds__(256) void k_init(InitArgs<R> a) {
-  const int64_t total = (int64_t)a.njobs * a.nbx;
-  const int64_t L = xcd_remap(blockIdx.x, total);
-  const int64_t job = L / a.nbx, bx = L - job * a.nbx;
-  const int64_t M = bx * kBlock + threadIdx.x;
-  if (M >= a.Z) return;
-  const cx<double> *t = a.tab + (int64_t)a.job_sample[job] * a.N * (RP_MAX_TWO_I + 1);
+  const int64_t L = xcd_remap(blockIdx.x, a.tiles);
+  int64_t M, Z, off;
+  const cx<double> *t;
+  int N;
+  const int32_t *stride, *d;
+  if constexpr (Q) {
+    const int64_t job = a.tile_job[L];
+    const QJob &j = a.jobs[job];
+    const SysArgs<R> &sa = a.systab[j.sys];
+    M = (L - j.blk) * kBlock + threadIdx.x;
+    Z = j.Z;
+    off = j.vec;
+    t = a.tab + j.tab * (RP_MAX_TWO_I + 1);
+    N = sa.N;
+    stride = sa.stride;
+    d = sa.d;
+  } else {
+    const int64_t job = L / a.nbx, bx = L - job * a.nbx;
+    M = bx * kBlock + threadIdx.x;
+    Z = a.Z;
+    off = job * (a.vstride ? a.vstride : a.Z * 4);
+    t = a.tab + (int64_t)a.job_sample[job] * a.N * (RP_MAX_TWO_I + 1);
+    N = a.N;
+    stride = a.stride;
+    d = a.d;
+  }
+  if (M >= Z) return;
   cx<double> p = {M_SQRT1_2, 0.0};
-  for (int k = 0; k < a.N; ++k) {
-    const int n = (int)((M / a.stride[k]) % a.d[k]);
+  for (int k = 0; k < N; ++k) {
+    const int n = (int)((M / stride[k]) % d[k]);
     const cx<double> c = t[k * (RP_MAX_TWO_I + 1) + n];
     p = {p.x * c.x - p.y * c.y, p.x * c.y + p.y * c.x};
   }
-  cx<R> *o = a.psi + job * (a.vstride ? a.vstride : a.Z * 4) + M;   // planes (aa, ab, ba, bb), each Z long
+  cx<R> *o = a.psi + off + M;   // planes (aa, ab, ba, bb), each Z long
   o[0] = {R(0), R(0)};
-  o[a.Z] = {R(p.x), R(p.y)};
-  o[2 * a.Z] = {R(-p.x), R(-p.y)};
-  o[3 * a.Z] = {R(0), R(0)};
+  o[Z] = {R(p.x), R(p.y)};
+  o[2 * Z] = {R(-p.x), R(-p.y)};
+  o[3 * Z] = {R(0), R(0)};
 }
 
 // ----------------------------------------------------------------------------- Chebyshev term
@@ -244,7 +301,7 @@ __device__ __forceinline__ void load2<float>(const cx<float> *p, cx<float> &a, c
   b = {v.z, v.w};
 }
 
-// Which step accumulator work a term launch does (see propagate_system).
+// Which step accumulator work a term launch does (see TiledRun::run).
 enum TermMode { kFirst = 0, kPlain = 1, kAcc3 = 2 };
 
 // Adds the flip-flop contribution of one spin-1/2 nucleus on radical 1 (r1) or 2, given
@@ -308,19 +365,20 @@ __device__ __forceinline__ cx<R> acc_value(cx<R> am, cx<R> a0, cx<R> ap, cx<R> v
 // term_z, then the stores of phi_{n+1}, its singlet amplitude and the accumulator.
 template <typename R, int MODE, bool NT>
 __device__ __forceinline__ void finish_term(const TermArgs<R> &ta, const SysArgs<R> &sa, const FieldDev<R> &fp,
-                                            int fi, int64_t job, int64_t M, R h1, R h2, cx<R> x0, cx<R> x1,
+                                            const TileRef &t, int64_t M, R h1, R h2, cx<R> x0, cx<R> x1,
                                             cx<R> x2, cx<R> x3, cx<R> o0, cx<R> o1, cx<R> o2, cx<R> o3,
                                             cx<R> y0, cx<R> y1, cx<R> y2, cx<R> y3) {
   cx<R> z0, z1, z2, z3;
   term_z<R, MODE>(sa, fp, h1, h2, x0, x1, x2, x3, o0, o1, o2, o3, y0, y1, y2, y3, z0, z1, z2, z3);
-  const int64_t Z = sa.Z;
-  const int64_t e = job * Z * 4 + M;
+  const int64_t Z = t.Z;
+  const int64_t e = t.vec + M;
+  const int fi = t.fi;
   cx<R> *O = ta.phio + e;
   st_nt<NT>(O, z0);
   st_nt<NT>(O + Z, z1);
   st_nt<NT>(O + 2 * Z, z2);
   st_nt<NT>(O + 3 * Z, z3);
-  st_nt<true>(ta.dnext + job * sa.Z + M, csub(z1, z2));
+  st_nt<true>(ta.dnext + t.amp + M, csub(z1, z2));
   const cx<R> *cf = ta.coef + (int64_t)fi * ta.n_terms;
   cx<R> *A = ta.acc + e;
   const cx<R> zero = {R(0), R(0)};
@@ -330,7 +388,7 @@ __device__ __forceinline__ void finish_term(const TermArgs<R> &ta, const SysArgs
     st_nt<NT>(A + Z, acc_value<R, MODE>(a0, a1, zero, zero, zero, x1, z1));
     st_nt<NT>(A + 2 * Z, acc_value<R, MODE>(a0, a1, zero, zero, zero, x2, z2));
     st_nt<NT>(A + 3 * Z, acc_value<R, MODE>(a0, a1, zero, zero, zero, x3, z3));
-    st_nt<true>(ta.dfirst + job * sa.Z + M, csub(x1, x2));
+    st_nt<true>(ta.dfirst + t.amp + M, csub(x1, x2));
   } else if (MODE == kAcc3) {
     const cx<R> am = cf[ta.n - 1], a0 = cf[ta.n], ap = cf[ta.n + 1];
     const cx<R> v0 = ld_nt<NT>(A), v1 = ld_nt<NT>(A + Z), v2 = ld_nt<NT>(A + 2 * Z),
@@ -349,20 +407,20 @@ __device__ __forceinline__ void finish_term(const TermArgs<R> &ta, const SysArgs
 // spin-1/2 axes are read from global memory in batches of 8 loads; higher spins follow with
 // workgroup-uniform digits.
 constexpr int kSlowBatch = 8;   // slow-axis partner loads issued together
-template <typename R, int MODE, bool NT>
-__global__ __launch_bounds__(256) void k_cheb_tile(TermArgs<R> ta, SysArgs<R> sa) {
+template <typename R, int MODE, bool NT, bool Q>
+__global__ __launch_bounds__(256) void k_cheb_tile(TermArgs<R> ta, SysArgs<R> sa1) {
   __shared__ cx<R> tile[kBlock * 4];
   __shared__ double lds[4];
-  const int64_t total = (int64_t)ta.njobs * ta.nbx;
-  const int64_t L = ta.remap ? xcd_remap(blockIdx.x, total) : (int64_t)blockIdx.x;
-  const int64_t job = L / ta.nbx, bx = L - job * ta.nbx;
+  const int64_t L = ta.remap ? xcd_remap(blockIdx.x, ta.tiles) : (int64_t)blockIdx.x;
+  const TileRef t = tile_ref<Q>(ta, L, sa1.Z);
+  const SysArgs<R> &sa = Q ? ta.systab[t.sys] : sa1;
+  const int64_t bx = t.bx;
   const int tid = threadIdx.x;
   const int64_t M = bx * kBlock + tid;
-  const bool live = M < sa.Z;
-  const int fi = ta.job_field[job];
-  const FieldDev<R> fp = ta.fields[fi];
-  const int64_t Z = sa.Z;
-  const cx<R> *X = ta.phin + job * Z * 4;
+  const int64_t Z = t.Z;
+  const bool live = M < Z;
+  const FieldDev<R> fp = ta.fields[t.fi];
+  const cx<R> *X = ta.phin + t.vec;
   const cx<R> zero = {R(0), R(0)};
   cx<R> x0 = zero, x1 = zero, x2 = zero, x3 = zero, o0 = zero, o1 = zero, o2 = zero, o3 = zero;
   if (live) {
@@ -371,7 +429,7 @@ __global__ __launch_bounds__(256) void k_cheb_tile(TermArgs<R> ta, SysArgs<R> sa
     x2 = X[2 * Z + M];
     x3 = X[3 * Z + M];
     if (MODE != kFirst) {
-      const cx<R> *O = ta.phio + job * Z * 4 + M;
+      const cx<R> *O = ta.phio + t.vec + M;
       o0 = ld_nt<NT>(O);
       o1 = ld_nt<NT>(O + Z);
       o2 = ld_nt<NT>(O + 2 * Z);
@@ -488,14 +546,14 @@ __global__ __launch_bounds__(256) void k_cheb_tile(TermArgs<R> ta, SysArgs<R> sa
         }
       }
     }
-    finish_term<R, MODE, NT>(ta, sa, fp, fi, job, M, h1, h2, x0, x1, x2, x3, o0, o1, o2, o3, y0, y1, y2, y3);
+    finish_term<R, MODE, NT>(ta, sa, fp, t, M, h1, h2, x0, x1, x2, x3, o0, o1, o2, o3, y0, y1, y2, y3);
     if (MODE == kFirst)
       nrm = (double)x0.x * x0.x + (double)x0.y * x0.y + (double)x1.x * x1.x + (double)x1.y * x1.y +
             (double)x2.x * x2.x + (double)x2.y * x2.y + (double)x3.x * x3.x + (double)x3.y * x3.y;
   }
   if (MODE == kFirst) {
-    const double t = block_sum(nrm, lds);
-    if (tid == 0) ta.part_norm[job * ta.nbx + bx] = t;
+    const double tot = block_sum(nrm, lds);
+    if (tid == 0) ta.part_norm[L] = tot;
   }
 }
 
@@ -557,23 +615,24 @@ __device__ __forceinline__ int pair_c1(bool r1, int bit) { return r1 ? 2 * bit +
 // first (Z a multiple of 256).
 constexpr int kPairThreads = kBlock / 2;
 constexpr int kPairBatch = 8;   // slow-axis partner pairs loaded together
-template <int MODE, bool NT>
-__global__ __launch_bounds__(kPairThreads) void k_cheb_pair(TermArgs<float> ta, SysArgs<float> sa) {
+template <int MODE, bool NT, bool Q>
+__global__ __launch_bounds__(kPairThreads) void k_cheb_pair(TermArgs<float> ta, SysArgs<float> sa1) {
   __shared__ f4 tile[4 * kPairThreads];
   __shared__ double lds[2];
-  const int64_t total = (int64_t)ta.njobs * ta.nbx;
-  const int64_t L = ta.remap ? xcd_remap(blockIdx.x, total) : (int64_t)blockIdx.x;
-  const int64_t job = L / ta.nbx, bx = L - job * ta.nbx;
+  const int64_t L = ta.remap ? xcd_remap(blockIdx.x, ta.tiles) : (int64_t)blockIdx.x;
+  const TileRef t = tile_ref<Q>(ta, L, sa1.Z);
+  const SysArgs<float> &sa = Q ? ta.systab[t.sys] : sa1;
+  const int64_t bx = t.bx;
   const int tid = threadIdx.x;
   const int64_t M = bx * kBlock + 2 * tid;
-  const int fi = ta.job_field[job];
+  const int fi = t.fi;
   const FieldDev<float> fp = ta.fields[fi];
-  const int64_t Z = sa.Z;
-  const cx<float> *X = ta.phin + job * Z * 4;
+  const int64_t Z = t.Z;
+  const cx<float> *X = ta.phin + t.vec;
   f4 xv[4], ov[4] = {};
   for (int e = 0; e < 4; ++e) xv[e] = ld4<false>(X + e * Z + M);
   if (MODE != kFirst) {
-    const cx<float> *O = ta.phio + job * Z * 4 + M;
+    const cx<float> *O = ta.phio + t.vec + M;
     for (int e = 0; e < 4; ++e) ov[e] = ld4<NT>(O + e * Z);
   }
   for (int e = 0; e < 4; ++e) tile[e * kPairThreads + tid] = xv[e];
@@ -680,10 +739,10 @@ __global__ __launch_bounds__(kPairThreads) void k_cheb_pair(TermArgs<float> ta, 
                       lo(ov[2]), lo(ov[3]), A.y0, A.y1, A.y2, A.y3, za[0], za[1], za[2], za[3]);
   term_z<float, MODE>(sa, fp, B.h1, B.h2, hi(xv[0]), hi(xv[1]), hi(xv[2]), hi(xv[3]), hi(ov[0]), hi(ov[1]),
                       hi(ov[2]), hi(ov[3]), B.y0, B.y1, B.y2, B.y3, zb[0], zb[1], zb[2], zb[3]);
-  const int64_t e0 = job * Z * 4 + M;
+  const int64_t e0 = t.vec + M;
   cx<float> *O = ta.phio + e0;
   for (int e = 0; e < 4; ++e) st4<NT>(O + e * Z, za[e], zb[e]);
-  st4<true>(ta.dnext + job * Z + M, csub(za[1], za[2]), csub(zb[1], zb[2]));
+  st4<true>(ta.dnext + t.amp + M, csub(za[1], za[2]), csub(zb[1], zb[2]));
   const cx<float> *cf = ta.coef + (int64_t)fi * ta.n_terms;
   cx<float> *Ac = ta.acc + e0;
   if (MODE == kFirst) {
@@ -691,7 +750,7 @@ __global__ __launch_bounds__(kPairThreads) void k_cheb_pair(TermArgs<float> ta, 
     for (int e = 0; e < 4; ++e)
       st4<NT>(Ac + e * Z, acc_value<float, MODE>(a0, a1, zero, zero, zero, lo(xv[e]), za[e]),
               acc_value<float, MODE>(a0, a1, zero, zero, zero, hi(xv[e]), zb[e]));
-    st4<true>(ta.dfirst + job * Z + M, csub(lo(xv[1]), lo(xv[2])), csub(hi(xv[1]), hi(xv[2])));
+    st4<true>(ta.dfirst + t.amp + M, csub(lo(xv[1]), lo(xv[2])), csub(hi(xv[1]), hi(xv[2])));
   } else if (MODE == kAcc3) {
     const cx<float> am = cf[ta.n - 1], a0 = cf[ta.n], ap = cf[ta.n + 1];
     f4 v[4];
@@ -708,30 +767,29 @@ __global__ __launch_bounds__(kPairThreads) void k_cheb_pair(TermArgs<float> ta, 
     nrm = warp_sum(nrm);
     if ((tid & 63) == 0) lds[tid >> 6] = nrm;
     __syncthreads();
-    if (tid == 0) ta.part_norm[job * ta.nbx + bx] = lds[0] + lds[1];
+    if (tid == 0) ta.part_norm[L] = lds[0] + lds[1];
   }
 }
 
 // One Chebyshev term for any mix of spins (mixed-radix digits, partners from global memory).
-template <typename R, int MODE, bool NT>
-__global__ __launch_bounds__(256) void k_cheb_gen(TermArgs<R> ta, SysArgs<R> sa) {
+template <typename R, int MODE, bool NT, bool Q>
+__global__ __launch_bounds__(256) void k_cheb_gen(TermArgs<R> ta, SysArgs<R> sa1) {
   __shared__ double lds[4];
-  const int64_t total = (int64_t)ta.njobs * ta.nbx;
-  const int64_t L = ta.remap ? xcd_remap(blockIdx.x, total) : (int64_t)blockIdx.x;
-  const int64_t job = L / ta.nbx, bx = L - job * ta.nbx;
-  const int64_t M = bx * kBlock + threadIdx.x;
-  const bool live = M < sa.Z;
-  const int fi = ta.job_field[job];
-  const FieldDev<R> fp = ta.fields[fi];
+  const int64_t L = ta.remap ? xcd_remap(blockIdx.x, ta.tiles) : (int64_t)blockIdx.x;
+  const TileRef t = tile_ref<Q>(ta, L, sa1.Z);
+  const SysArgs<R> &sa = Q ? ta.systab[t.sys] : sa1;
+  const int64_t M = t.bx * kBlock + threadIdx.x;
+  const bool live = M < t.Z;
+  const FieldDev<R> fp = ta.fields[t.fi];
   double nrm = 0.0;
   if (live) {
     const cx<R> zero = {R(0), R(0)};
-    const int64_t Z = sa.Z;
-    const cx<R> *X = ta.phin + job * Z * 4;
+    const int64_t Z = t.Z;
+    const cx<R> *X = ta.phin + t.vec;
     cx<R> o0 = zero, o1 = zero, o2 = zero, o3 = zero;
     const cx<R> x0 = X[M], x1 = X[Z + M], x2 = X[2 * Z + M], x3 = X[3 * Z + M];
     if (MODE != kFirst) {
-      const cx<R> *O = ta.phio + job * Z * 4 + M;
+      const cx<R> *O = ta.phio + t.vec + M;
       o0 = ld_nt<NT>(O);
       o1 = ld_nt<NT>(O + Z);
       o2 = ld_nt<NT>(O + 2 * Z);
@@ -772,14 +830,14 @@ __global__ __launch_bounds__(256) void k_cheb_gen(TermArgs<R> ta, SysArgs<R> sa)
         }
       }
     }
-    finish_term<R, MODE, NT>(ta, sa, fp, fi, job, M, h1, h2, x0, x1, x2, x3, o0, o1, o2, o3, y0, y1, y2, y3);
+    finish_term<R, MODE, NT>(ta, sa, fp, t, M, h1, h2, x0, x1, x2, x3, o0, o1, o2, o3, y0, y1, y2, y3);
     if (MODE == kFirst)
       nrm = (double)x0.x * x0.x + (double)x0.y * x0.y + (double)x1.x * x1.x + (double)x1.y * x1.y +
             (double)x2.x * x2.x + (double)x2.y * x2.y + (double)x3.x * x3.x + (double)x3.y * x3.y;
   }
   if (MODE == kFirst) {
-    const double t = block_sum(nrm, lds);
-    if (threadIdx.x == 0) ta.part_norm[job * ta.nbx + bx] = t;
+    const double tot = block_sum(nrm, lds);
+    if (threadIdx.x == 0) ta.part_norm[L] = tot;
   }
 }
 
@@ -791,17 +849,16 @@ __global__ __launch_bounds__(256) void k_cheb_gen(TermArgs<R> ta, SysArgs<R> sa)
 template <typename R>
 using const_ptr = const __attribute__((address_space(4))) R *;
 
-template <typename R, int RC>
+template <typename R, int RC, bool Q>
 __global__ __launch_bounds__(256) void k_quad(QuadArgs<R> qa) {
   __shared__ double lds[4];
-  const int64_t total = (int64_t)qa.njobs * qa.nbx;
-  const int64_t L = qa.remap ? xcd_remap(blockIdx.x, total) : (int64_t)blockIdx.x;
-  const int64_t job = L / qa.nbx, bx = L - job * qa.nbx;
-  const int64_t M = bx * kBlock + threadIdx.x;
-  const bool live = M < qa.Z;
-  const int fi = __builtin_amdgcn_readfirstlane(qa.job_field[job]);
+  const int64_t L = qa.remap ? xcd_remap(blockIdx.x, qa.tiles) : (int64_t)blockIdx.x;
+  const TileRef t = tile_ref<Q>(qa, L, qa.Z);
+  const int64_t M = t.bx * kBlock + threadIdx.x;
+  const bool live = M < t.Z;
+  const int fi = __builtin_amdgcn_readfirstlane(t.fi);
   const_ptr<R> ell = (const_ptr<R>)(qa.ell + (int64_t)fi * qa.n_terms * qa.rank_pad);
-  const cx<R> *dp = qa.d + job * qa.Z + (live ? M : 0);
+  const cx<R> *dp = qa.d + t.amp + (live ? M : 0);
   double acc = 0.0, ps = 0.0;
   if (live) {
     for (int r0 = 0; r0 < qa.rank_pad; r0 += RC) {
@@ -838,53 +895,68 @@ __global__ __launch_bounds__(256) void k_quad(QuadArgs<R> qa) {
   const double s0 = block_sum(acc, lds);
   const double s1 = block_sum(ps, lds);
   if (threadIdx.x == 0) {
-    qa.part[(job * qa.nbx + bx) * 2] = s0;
-    qa.part[(job * qa.nbx + bx) * 2 + 1] = s1;
+    qa.part[L * 2] = s0;
+    qa.part[L * 2 + 1] = s1;
   }
 }
 
 // Term kernel variants: any mix of spins, the 256-index tile, and the tile on index pairs.
 enum TermKernel { kTermGen = 0, kTermTile = 1, kTermPair = 2 };
 
-template <typename R, int MODE, bool NT>
-static void launch_term_t(int kind, unsigned grid, hipStream_t st, const TermArgs<R> &ta, const SysArgs<R> &sa) {
+template <typename R, int MODE, bool NT, bool Q>
+static void launch_term_q(int kind, unsigned grid, hipStream_t st, const TermArgs<R> &ta, const SysArgs<R> &sa) {
   if constexpr (std::is_same<R, float>::value) {
     if (kind == kTermPair) {
-      hipLaunchKernelGGL((k_cheb_pair<MODE, NT>), dim3(grid), dim3(kPairThreads), 0, st, ta, sa);
+      hipLaunchKernelGGL((k_cheb_pair<MODE, NT, Q>), dim3(grid), dim3(kPairThreads), 0, st, ta, sa);
       return;
     }
   }
   if (kind == kTermGen)
-    hipLaunchKernelGGL((k_cheb_gen<R, MODE, NT>), dim3(grid), dim3(kBlock), 0, st, ta, sa);
+    hipLaunchKernelGGL((k_cheb_gen<R, MODE, NT, Q>), dim3(grid), dim3(kBlock), 0, st, ta, sa);
   else
-    hipLaunchKernelGGL((k_cheb_tile<R, MODE, NT>), dim3(grid), dim3(kBlock), 0, st, ta, sa);
+    hipLaunchKernelGGL((k_cheb_tile<R, MODE, NT, Q>), dim3(grid), dim3(kBlock), 0, st, ta, sa);
 }
 
+template <typename R, int MODE, bool NT>
+static void launch_term_t(int kind, bool q, unsigned grid, hipStream_t st, const TermArgs<R> &ta,
+                          const SysArgs<R> &sa) {
+  if (q) launch_term_q<R, MODE, NT, true>(kind, grid, st, ta, sa);
+  else launch_term_q<R, MODE, NT, false>(kind, grid, st, ta, sa);
+}
+
+// q: the launch spans the job queue of several systems (per-job descriptors) rather than the
+// jobs of one system.
 template <typename R>
-static void launch_term(int mode, int kind, bool nt, unsigned grid, hipStream_t st, const TermArgs<R> &ta,
+static void launch_term(int mode, int kind, bool nt, bool q, unsigned grid, hipStream_t st, const TermArgs<R> &ta,
                         const SysArgs<R> &sa) {
   switch (mode * 2 + (nt ? 1 : 0)) {
-    case kFirst * 2: launch_term_t<R, kFirst, false>(kind, grid, st, ta, sa); break;
-    case kFirst * 2 + 1: launch_term_t<R, kFirst, true>(kind, grid, st, ta, sa); break;
-    case kPlain * 2: launch_term_t<R, kPlain, false>(kind, grid, st, ta, sa); break;
-    case kPlain * 2 + 1: launch_term_t<R, kPlain, true>(kind, grid, st, ta, sa); break;
-    case kAcc3 * 2: launch_term_t<R, kAcc3, false>(kind, grid, st, ta, sa); break;
-    default: launch_term_t<R, kAcc3, true>(kind, grid, st, ta, sa); break;
+    case kFirst * 2: launch_term_t<R, kFirst, false>(kind, q, grid, st, ta, sa); break;
+    case kFirst * 2 + 1: launch_term_t<R, kFirst, true>(kind, q, grid, st, ta, sa); break;
+    case kPlain * 2: launch_term_t<R, kPlain, false>(kind, q, grid, st, ta, sa); break;
+    case kPlain * 2 + 1: launch_term_t<R, kPlain, true>(kind, q, grid, st, ta, sa); break;
+    case kAcc3 * 2: launch_term_t<R, kAcc3, false>(kind, q, grid, st, ta, sa); break;
+    default: launch_term_t<R, kAcc3, true>(kind, q, grid, st, ta, sa); break;
+  }
+}
+
+template <typename R, bool Q>
+static void launch_quad_q(int rcw, unsigned grid, hipStream_t st, const QuadArgs<R> &qa) {
+  switch (rcw) {
+    case 64: hipLaunchKernelGGL((k_quad<R, 64, Q>), dim3(grid), dim3(kBlock), 0, st, qa); break;
+    case 56: hipLaunchKernelGGL((k_quad<R, 56, Q>), dim3(grid), dim3(kBlock), 0, st, qa); break;
+    case 48: hipLaunchKernelGGL((k_quad<R, 48, Q>), dim3(grid), dim3(kBlock), 0, st, qa); break;
+    case 40: hipLaunchKernelGGL((k_quad<R, 40, Q>), dim3(grid), dim3(kBlock), 0, st, qa); break;
+    case 32: hipLaunchKernelGGL((k_quad<R, 32, Q>), dim3(grid), dim3(kBlock), 0, st, qa); break;
+    case 24: hipLaunchKernelGGL((k_quad<R, 24, Q>), dim3(grid), dim3(kBlock), 0, st, qa); break;
+    case 16: hipLaunchKernelGGL((k_quad<R, 16, Q>), dim3(grid), dim3(kBlock), 0, st, qa); break;
+    default: hipLaunchKernelGGL((k_quad<R, 8, Q>), dim3(grid), dim3(kBlock), 0, st, qa); break;
   }
 }
 
 template <typename R>
-static void launch_quad(int rcw, unsigned grid, hipStream_t st, const QuadArgs<R> &qa) {
-  switch (rcw) {
-    case 64: hipLaunchKernelGGL((k_quad<R, 64>), dim3(grid), dim3(kBlock), 0, st, qa); break;
-    case 56: hipLaunchKernelGGL((k_quad<R, 56>), dim3(grid), dim3(kBlock), 0, st, qa); break;
-    case 48: hipLaunchKernelGGL((k_quad<R, 48>), dim3(grid), dim3(kBlock), 0, st, qa); break;
-    case 40: hipLaunchKernelGGL((k_quad<R, 40>), dim3(grid), dim3(kBlock), 0, st, qa); break;
-    case 32: hipLaunchKernelGGL((k_quad<R, 32>), dim3(grid), dim3(kBlock), 0, st, qa); break;
-    case 24: hipLaunchKernelGGL((k_quad<R, 24>), dim3(grid), dim3(kBlock), 0, st, qa); break;
-    case 16: hipLaunchKernelGGL((k_quad<R, 16>), dim3(grid), dim3(kBlock), 0, st, qa); break;
-    default: hipLaunchKernelGGL((k_quad<R, 8>), dim3(grid), dim3(kBlock), 0, st, qa); break;
-  }
+static void launch_quad(int rcw, bool q, unsigned grid, hipStream_t st, const QuadArgs<R> &qa) {
+  if (q) launch_quad_q<R, true>(rcw, grid, st, qa);
+  else launch_quad_q<R, false>(rcw, grid, st, qa);
 }
 
 // ----------------------------------------------------------------------------- LDS-resident propagation
@@ -1091,21 +1163,33 @@ __global__ __launch_bounds__(MAXB) void k_resident(ResArgs<R> ra) {
 __global__ __launch_bounds__(256) void k_finalize(FinArgs fa) {
   __shared__ double lds[4];
   const int64_t job = blockIdx.x;
+  int64_t b0 = job * fa.nbx, nb = fa.nbx;
+  int fi;
+  double kS = fa.kS, kmin = fa.kmin;
+  if (fa.jobs) {   // job queue: the job's own tiles and rates
+    const QJob &j = fa.jobs[job];
+    b0 = j.blk;
+    nb = j.nbx;
+    fi = j.field;
+    kS = fa.sys_k[2 * j.sys];
+    kmin = fa.sys_k[2 * j.sys + 1];
+  } else {
+    fi = fa.job_field[job];
+  }
   double y = 0.0, nrm = 0.0, ps = 0.0;
-  for (int64_t b = threadIdx.x; b < fa.nbx; b += kBlock) {
-    y += fa.part_q[(job * fa.nbx + b) * 2];
-    nrm += fa.part_norm[job * fa.nbx + b];
-    if (fa.ps_t) ps += fa.part_q[(job * fa.nbx + b) * 2 + 1];
+  for (int64_t b = threadIdx.x; b < nb; b += kBlock) {
+    y += fa.part_q[(b0 + b) * 2];
+    nrm += fa.part_norm[b0 + b];
+    if (fa.ps_t) ps += fa.part_q[(b0 + b) * 2 + 1];
   }
   y = block_sum(y, lds);
   nrm = block_sum(nrm, lds);
   if (fa.ps_t) ps = block_sum(ps, lds);
   if (threadIdx.x != 0) return;
-  const int fi = fa.job_field[job];
   const int32_t step = fa.stepc[job];
   fa.stepc[job] = step + 1;
-  const double decay = exp(-fa.kmin * step * fa.dt[fi]);
-  fa.phi[job] += fa.kS * decay * y;
+  const double decay = exp(-kmin * step * fa.dt[fi]);
+  fa.phi[job] += kS * decay * y;
   if (fa.ps_t && step < fa.ps_len) fa.ps_t[fa.dst[job] * fa.ps_len + step] = decay * ps;
   const double Nt = decay * nrm;           // population N(t_j) of the wavepacket
   if (!(Nt <= fa.prev_norm[job] * (1.0 + fa.rtol) + 1e-300) || !(y == y)) atomicOr(fa.flag, 1);
@@ -1324,25 +1408,6 @@ static int read_opts(const rp_opts *o, Opts &out) {
   return RP_OK;
 }
 
-// Plans every field of one system, in parallel over host threads.
-static int plan_all(const SystemSpec &spec, const double *B, int nB, const Opts &op,
-                    std::vector<FieldPlan> &plans) {
-  plans.assign(nB, FieldPlan());
-  std::vector<std::string> msgs(nB);
-  std::vector<char> ok(nB, 0);
-  const int nth = std::max(1, std::min<int>(nB, (int)std::thread::hardware_concurrency()));
-  std::vector<std::thread> th;
-  for (int t = 0; t < nth; ++t)
-    th.emplace_back([&, t]() {
-      for (int b = t; b < nB; b += nth)
-        ok[b] = plan_field(spec, B[b], op.tol, op.rdt, op.r_scale, op.chol_tol, op.max_growth, plans[b], msgs[b]);
-    });
-  for (auto &x : th) x.join();
-  for (int b = 0; b < nB; ++b)
-    if (!ok[b]) return fail(RP_EINVAL, "field " + std::to_string(b) + ": " + msgs[b]);
-  return RP_OK;
-}
-
 template <typename R>
 static SysArgs<R> make_sysargs(const SystemSpec &s) {
   SysArgs<R> a;
@@ -1379,526 +1444,852 @@ static SysArgs<R> make_sysargs(const SystemSpec &s) {
 
 static unsigned grid1(int64_t n) { return (unsigned)((n + 255) / 256); }
 
-// Propagates every (field, sample) job of one system; writes phi_out[b][s] (device).
-template <typename R>
-static int propagate_system(const SystemSpec &spec, const double *B, int nB, const double *angles_dev,
-                            int64_t M, const Opts &op, double *phi_out, double *ps_out, hipStream_t st,
-                            EventLog &log) {
-  std::vector<FieldPlan> plans;
-  int rc = plan_all(spec, B, nB, op, plans);
-  if (rc) return rc;
-  const int64_t Z = spec.Z;
-  const int N = spec.N();
-  // Fields sorted by decreasing step count: the jobs still running at any step form a prefix.
-  std::vector<int> order(nB);
-  std::iota(order.begin(), order.end(), 0);
-  std::stable_sort(order.begin(), order.end(),
-                   [&](int a, int b) { return plans[a].n_steps > plans[b].n_steps; });
-  int nt = 1, rk = 1;
-  for (auto &p : plans) {
-    nt = std::max(nt, p.n_terms);
-    rk = std::max(rk, p.rank);
-  }
-  // Pad the term count so that (nt - 2) is a multiple of 3: the accumulator is updated
-  // by the first launch (terms 0, 1) and then by every third launch (three terms each).
-  while ((nt - 2) % 3 != 0) ++nt;
-  // k_quad makes passes of rcw <= 64 (FP32) or 32 (FP64) columns, each reading every singlet
-  // amplitude once: the fewest passes that cover the rank, of equal width (a multiple of 8),
-  // with the rank padded by zero columns to passes * rcw.
-  const int wmax = sizeof(R) == 4 ? 64 : 32;
-  const int passes = (rk + wmax - 1) / wmax;
-  const int rcw = ((rk + passes - 1) / passes + 7) / 8 * 8;
-  const int rkp = passes * rcw;
-  std::vector<FieldDev<R>> fdev(nB);
-  std::vector<cx<R>> coef((size_t)nB * nt, cx<R>{R(0), R(0)});
-  std::vector<R> ell((size_t)nB * nt * rkp, R(0));
-  std::vector<double> dts(nB);
-  std::vector<int64_t> nsteps(nB);
-  const double dk = std::fabs(spec.kS - spec.kT);
-  for (int f = 0; f < nB; ++f) {
-    const FieldPlan &p = plans[order[f]];
-    FieldDev<R> d;
-    d.omega = (R)p.omega;
-    d.c_re = (R)p.c_re;
-    d.c_im = (R)(p.c_im + (spec.kS >= spec.kT ? 0.0 : 0.5 * dk));
-    d.s1 = (R)(1.0 / p.r);
-    d.s2 = (R)(2.0 / p.r);
-    fdev[f] = d;
-    for (int n = 0; n < p.n_terms; ++n) coef[(size_t)f * nt + n] = {(R)p.coef[n].real(), (R)p.coef[n].imag()};
-    for (int n = 0; n < p.n_terms; ++n)
-      for (int r = 0; r < p.rank; ++r) ell[((size_t)f * nt + n) * rkp + r] = (R)p.ell[(size_t)n * p.rank + r];
-    dts[f] = p.dt;
-    nsteps[f] = p.n_steps;
-  }
-  const int64_t total_jobs = (int64_t)nB * M;
-  if (total_jobs == 0) return RP_OK;
-  std::vector<int32_t> job_field(total_jobs), job_sample(total_jobs);
-  std::vector<int64_t> dst(total_jobs);
-  for (int f = 0; f < nB; ++f)
-    for (int64_t s = 0; s < M; ++s) {
-      const int64_t j = (int64_t)f * M + s;
-      job_field[j] = f;
-      job_sample[j] = (int32_t)s;
-      dst[j] = (int64_t)order[f] * M + s;
+// Device workspace of one call, carved from one block: the block rp_propagate allocates for
+// the call on its stream, or the library's static scratch area (rp_propagate_static).  Every
+// piece is 256-byte aligned; Sizer counts the same rounding, so a layout measured with Sizer
+// fits an Arena of that many bytes exactly.
+static int64_t round256(int64_t bytes) { return (std::max<int64_t>(bytes, 1) + 255) & ~int64_t(255); }
+struct Sizer {
+  int64_t used = 0;
+  template <typename T>
+  void add(int64_t n) { used += round256(n * (int64_t)sizeof(T)); }
+};
+struct Arena {
+  char *base = nullptr;
+  int64_t cap = 0, used = 0;
+  bool overflow = false;
+  template <typename T>
+  T *take(int64_t n) {
+    const int64_t b = round256(n * (int64_t)sizeof(T));
+    if (used + b > cap) {
+      overflow = true;
+      return nullptr;
     }
-  const int64_t nbx = (Z + kBlock - 1) / kBlock;
-  const int64_t vec_bytes = 4 * Z * (int64_t)sizeof(cx<R>);
-  const int64_t per_job = 3 * vec_bytes + (int64_t)nt * Z * sizeof(cx<R>) + nbx * 3 * 8 + 32;
-  int64_t budget = op.workspace;
-  if (budget <= 0) {
-    size_t fr = 0, tot = 0;
-    HIPCHK(hipMemGetInfo(&fr, &tot));
-    budget = (int64_t)(fr / 2);
+    T *p = reinterpret_cast<T *>(base + used);
+    used += b;
+    return p;
   }
-  int64_t chunk = std::min<int64_t>(total_jobs, budget / per_job);
-  if (chunk < 1) return fail(RP_ENOMEM, "workspace too small for one wavepacket");
-  if (op.workspace <= 0) {
-    // Default chunk: the three wavepacket buffers of the chunk (about 192 MB) stay resident in
-    // the 256 MB Infinity Cache across launches, but every launch keeps at least 64 jobs.
-    const int64_t resident = std::max<int64_t>(64, ((int64_t)192 << 20) / (3 * vec_bytes));
-    chunk = std::min(chunk, resident);
-  }
-  chunk = std::min<int64_t>(chunk, (((int64_t)1) << 24) / nbx);   // grid of < 2^24 workgroups
+};
 
-  // Device allocations.
-  struct Buf {
-    void *p = nullptr;
-    ~Buf() { if (p) (void)hipFree(p); }
-  };
-  Buf bP0, bP1, bP2, bD, bPn, bPq, bPhi, bPrev, bFlag, bFd, bCoef, bEll, bDt, bJf, bJs, bDst, bTab, bOut, bStep;
-  auto alloc = [&](Buf &b, size_t bytes) -> int {
-    if (hipMalloc(&b.p, std::max<size_t>(bytes, 16)) != hipSuccess) {
-      (void)hipGetLastError();
-      return fail(RP_ENOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes failed");
-    }
-    return RP_OK;
-  };
-#define ALLOC(b, n)              \
-  do {                           \
-    int rc_ = alloc(b, (n));     \
-    if (rc_) return rc_;         \
-  } while (0)
-  ALLOC(bP0, chunk * vec_bytes);
-  ALLOC(bP1, chunk * vec_bytes);
-  ALLOC(bP2, chunk * vec_bytes);
-  ALLOC(bD, (size_t)nt * chunk * Z * sizeof(cx<R>));
-  ALLOC(bPn, chunk * nbx * 8);
-  ALLOC(bPq, chunk * nbx * 16);
-  ALLOC(bPhi, chunk * 8);
-  ALLOC(bPrev, chunk * 8);
-  ALLOC(bStep, chunk * 4);
-  ALLOC(bFlag, 16);
-  ALLOC(bFd, nB * sizeof(FieldDev<R>));
-  ALLOC(bCoef, coef.size() * sizeof(cx<R>));
-  ALLOC(bEll, ell.size() * sizeof(R));
-  ALLOC(bDt, nB * 8);
-  ALLOC(bJf, total_jobs * 4);
-  ALLOC(bJs, total_jobs * 4);
-  ALLOC(bDst, total_jobs * 8);
-  ALLOC(bTab, (size_t)std::max<int64_t>(M, 1) * std::max(N, 1) * (RP_MAX_TWO_I + 1) * sizeof(cx<double>));
-#undef ALLOC
-  HIPCHK(hipMemcpyAsync(bFd.p, fdev.data(), nB * sizeof(FieldDev<R>), hipMemcpyHostToDevice, st));
-  HIPCHK(hipMemcpyAsync(bCoef.p, coef.data(), coef.size() * sizeof(cx<R>), hipMemcpyHostToDevice, st));
-  HIPCHK(hipMemcpyAsync(bEll.p, ell.data(), ell.size() * sizeof(R), hipMemcpyHostToDevice, st));
-  HIPCHK(hipMemcpyAsync(bDt.p, dts.data(), nB * 8, hipMemcpyHostToDevice, st));
-  HIPCHK(hipMemcpyAsync(bJf.p, job_field.data(), total_jobs * 4, hipMemcpyHostToDevice, st));
-  HIPCHK(hipMemcpyAsync(bJs.p, job_sample.data(), total_jobs * 4, hipMemcpyHostToDevice, st));
-  HIPCHK(hipMemcpyAsync(bDst.p, dst.data(), total_jobs * 8, hipMemcpyHostToDevice, st));
-  HIPCHK(hipMemsetAsync(bFlag.p, 0, 16, st));
-  if (ps_out) {   // time points past a field's last step stay NaN
-    const int64_t n = total_jobs * op.ps_len;
-    hipLaunchKernelGGL(k_fill, dim3(grid1(n)), dim3(256), 0, st, ps_out, n, std::nan(""));
-    HIPCHK(hipGetLastError());
-  }
+__global__ __launch_bounds__(256) void k_fill_i32(int32_t *p, int64_t n, int32_t v) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
 
-  // Coherent-state components of every sample (shared by all fields).
-  if (N > 0 && M > 0) {
-    CohArgs ca;
-    std::memset(&ca, 0, sizeof(ca));
-    ca.angles = angles_dev;
-    ca.tab = (cx<double> *)bTab.p;
-    ca.M = M;
-    ca.N = N;
-    ca.mode = op.init_mode;
-    for (int k = 0; k < N; ++k) {
-      ca.two_I[k] = spec.two_I[k];
-      ca.perm[k] = spec.perm[k];
-    }
-    hipLaunchKernelGGL(k_coherent, dim3(grid1(M * N)), dim3(256), 0, st, ca);
-    HIPCHK(hipGetLastError());
-  }
-  const SysArgs<R> sa = make_sysargs<R>(spec);
-  const double kmin = std::min(spec.kS, spec.kT);
-  // Block order: a wavepacket that fits an XCD's 4 MB L2 comfortably is given to one XCD
-  // (its partner tiles stay in that L2); larger ones are spread over all XCDs, so that the
-  // whole GPU works on few wavepackets at a time and far partners hit the Infinity Cache.
-  int remap = vec_bytes <= ((int64_t)1 << 20) ? 1 : 0;
-  if (op.flags & RP_FLAG_XCD_LOCAL) remap = 1;
-  if (op.flags & RP_FLAG_XCD_SPREAD) remap = 0;
-  // Streaming (non-temporal) loads and stores of phi_{n-1}, phi_{n+1} and the accumulator when
-  // the chunk's three wavepacket buffers exceed the 256 MB Infinity Cache: they would not
-  // survive there until the next launch anyway, and the hint leaves the L2 to the partner
-  // tiles of phi_n.  The singlet amplitudes, read only by the quadrature, always stream.
-  const bool stream_nt = 3 * chunk * vec_bytes > ((int64_t)256 << 20);
-  // Term kernel: index pairs (complex FP32, at least 8 leading spin-1/2 nuclei), else the
-  // 256-index tile, else the generic form.
-  int term_kind = sa.tiled ? kTermTile : kTermGen;
-  if (std::is_same<R, float>::value && sa.tiled && sa.nhalf >= 8 && !(op.flags & RP_FLAG_TERM_SCALAR))
-    term_kind = kTermPair;
-  const double rtol = op.precision == 64 ? 1e-9 : 1e-4;
-  // Graph replay of the step launches (not while profiling: the events are per launch).
-  const bool use_graph = !log.on && !(op.flags & RP_FLAG_NO_GRAPH);
-
-  cx<R> *bufs[3] = {(cx<R> *)bP0.p, (cx<R> *)bP1.p, (cx<R> *)bP2.p};
-  for (int64_t j0 = 0; j0 < total_jobs; j0 += chunk) {
-    const int64_t nj = std::min(chunk, total_jobs - j0);
-    const int32_t *jf = (const int32_t *)bJf.p + j0;
-    // initial wavepackets
-    {
-      InitArgs<R> ia;
-      std::memset(&ia, 0, sizeof(ia));
-      ia.psi = bufs[0];
-      ia.tab = (const cx<double> *)bTab.p;
-      ia.job_sample = (const int32_t *)bJs.p + j0;
-      ia.Z = Z;
-      ia.nbx = nbx;
-      ia.njobs = (int32_t)nj;
-      ia.N = N;
-      for (int k = 0; k < N; ++k) {
-        ia.stride[k] = sa.stride[k];
-        ia.d[k] = sa.d[k];
-      }
-      if (N == 0) {
-        ia.stride[0] = 1;
-        ia.d[0] = 1;
-      }
-      hipLaunchKernelGGL(k_init<R>, dim3((unsigned)(nj * nbx)), dim3(kBlock), 0, st, ia);
-      HIPCHK(hipGetLastError());
-    }
-    hipLaunchKernelGGL(k_fill, dim3(grid1(nj)), dim3(256), 0, st, (double *)bPhi.p, nj, 0.0);
-    hipLaunchKernelGGL(k_fill, dim3(grid1(nj)), dim3(256), 0, st, (double *)bPrev.p, nj, 1.0 + 1e-6);
-    HIPCHK(hipGetLastError());
-    HIPCHK(hipMemsetAsync(bStep.p, 0, nj * 4, st));
-    int ip = 0, ia_ = 2, iodd = 1;   // psi, accumulator and odd-term buffers
-    const int64_t slab = nj * Z;
-    cx<R> *D = (cx<R> *)bD.p;
-    // All launches of one step: Chebyshev terms, in-step quadrature, finalisation.
-    auto enqueue_step = [&](int64_t active, int ipsi, int iacc) {
-      const unsigned grid = (unsigned)(active * nbx);
-      TermArgs<R> ta;
-      std::memset(&ta, 0, sizeof(ta));
-      ta.fields = (const FieldDev<R> *)bFd.p;
-      ta.coef = (const cx<R> *)bCoef.p;
-      ta.job_field = jf;
-      ta.part_norm = (double *)bPn.p;
-      ta.nbx = nbx;
-      ta.njobs = (int32_t)active;
-      ta.n_terms = nt;
-      ta.remap = remap;
-      ta.acc = bufs[iacc];
-      cx<R> *even = bufs[ipsi], *odd = bufs[iodd];
-      // n = 0: phi_1 = Gh phi_0
-      ta.phin = even;
-      ta.phio = odd;
-      ta.n = 0;
-      ta.dnext = D + slab;
-      ta.dfirst = D;
-      const double eb = (double)sizeof(R) / 4.0;   // bytes per element, in units of complex-FP32 bytes
-      log.mark(st);
-      launch_term<R>(kFirst, term_kind, stream_nt, grid, st, ta, sa);
-      double bytes = 28.0 * eb;
-      for (int n = 1; n + 1 < nt; ++n) {
-        // phi_{n+1} = 2 Gh phi_n - phi_{n-1}, written over phi_{n-1}; every third launch also adds
-        // phi_{n-1}, phi_n, phi_{n+1} to the step accumulator.
-        ta.phin = (n & 1) ? odd : even;
-        ta.phio = (n & 1) ? even : odd;
-        ta.n = n;
-        ta.dnext = D + (int64_t)(n + 1) * slab;
-        const bool acc3 = (n % 3) == 0;
-        launch_term<R>(acc3 ? kAcc3 : kPlain, term_kind, stream_nt, grid, st, ta, sa);
-        bytes += (acc3 ? 42.0 : 26.0) * eb;
-      }
-      log.mark(st);
-      log.close(0);
-      if (log.on) {
-        g_prof.term_launches += nt - 1;
-        g_prof.elems += (double)(nt - 1) * (double)active * 4.0 * (double)Z;
-        g_prof.bytes += bytes * (double)active * 4.0 * (double)Z;
-        g_prof.quad_launches += 1;
-        g_prof.terms = nt;
-      }
-      QuadArgs<R> qa;
-      std::memset(&qa, 0, sizeof(qa));
-      qa.d = D;
-      qa.slab = slab;
-      qa.ell = (const R *)bEll.p;
-      qa.job_field = jf;
-      qa.part = (double *)bPq.p;
-      qa.Z = Z;
-      qa.nbx = nbx;
-      qa.njobs = (int32_t)active;
-      qa.n_terms = nt;
-      qa.rank_pad = rkp;
-      qa.remap = remap;
-      log.mark(st);
-      launch_quad<R>(rcw, grid, st, qa);
-      log.mark(st);
-      log.close(1);
-      FinArgs fa;
-      std::memset(&fa, 0, sizeof(fa));
-      fa.part_q = (const double *)bPq.p;
-      fa.part_norm = (const double *)bPn.p;
-      fa.phi = (double *)bPhi.p;
-      fa.prev_norm = (double *)bPrev.p;
-      fa.flag = (int *)bFlag.p;
-      fa.job_field = jf;
-      fa.dt = (const double *)bDt.p;
-      fa.stepc = (int32_t *)bStep.p;
-      fa.nbx = nbx;
-      fa.njobs = (int32_t)active;
-      fa.kS = spec.kS;
-      fa.kmin = kmin;
-      fa.rtol = rtol;
-      fa.ps_t = ps_out;
-      fa.dst = (const int64_t *)bDst.p + j0;
-      fa.ps_len = op.ps_len;
-      hipLaunchKernelGGL(k_finalize, dim3((unsigned)active), dim3(kBlock), 0, st, fa);
-    };
-    // One captured graph per (active jobs, buffer parity) of this chunk, replayed every step.
-    using GraphKey = std::pair<int64_t, int>;
-    std::map<GraphKey, hipGraphExec_t> graphs;
-    // HIP does not promise that destroying an executable graph waits for its launches, so the
-    // chunk's launches are waited for before its graphs are destroyed.
-    struct GraphsGuard {
-      std::map<GraphKey, hipGraphExec_t> &g;
-      hipStream_t s;
-      ~GraphsGuard() {
-        if (g.empty()) return;
-        (void)hipStreamSynchronize(s);
-        for (auto &kv : g) (void)hipGraphExecDestroy(kv.second);
-      }
-    } graphs_guard{graphs, st};
-    const int64_t steps_max = nsteps[job_field[j0]];
-    for (int64_t t = 0; t < steps_max; ++t) {
-      // Jobs of fields with more than t steps form the prefix [0, C(t)) of the sorted list.
-      int64_t nf = 0;
-      while (nf < nB && nsteps[nf] > t) ++nf;
-      const int64_t active = std::min<int64_t>(nj, std::max<int64_t>(0, nf * M - j0));
-      if (active <= 0) break;
-      if (use_graph) {
-        const GraphKey key{active, ip};
-        auto it = graphs.find(key);
-        if (it == graphs.end()) {
-          HIPCHK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
-          enqueue_step(active, ip, ia_);
-          hipGraph_t g = nullptr;
-          const hipError_t ec = hipStreamEndCapture(st, &g);
-          if (ec != hipSuccess || !g) return fail(RP_EDEVICE, std::string("graph capture: ") + hipGetErrorString(ec));
-          hipGraphExec_t ge = nullptr;
-          const hipError_t ei = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
-          (void)hipGraphDestroy(g);
-          if (ei != hipSuccess) return fail(RP_EDEVICE, std::string("graph instantiate: ") + hipGetErrorString(ei));
-          it = graphs.emplace(key, ge).first;
-        }
-        HIPCHK(hipGraphLaunch(it->second, st));
-      } else {
-        enqueue_step(active, ip, ia_);
-        HIPCHK(hipGetLastError());
-      }
-      std::swap(ip, ia_);
-    }
-    hipLaunchKernelGGL(k_scatter, dim3(grid1(nj)), dim3(256), 0, st, (const double *)bPhi.p,
-                       (const int64_t *)bDst.p + j0, phi_out, nj);
-    HIPCHK(hipGetLastError());
-  }
-  int flag = 0;
-  HIPCHK(hipMemcpyAsync(&flag, bFlag.p, sizeof(int), hipMemcpyDeviceToHost, st));
-  HIPCHK(hipStreamSynchronize(st));
-  if (flag) return fail(RP_ENOTCONV, "wavepacket norm grew or became NaN (spectral bound violated)");
+// Plans every (system, field) pair of a call on host threads.
+static int plan_many(const std::vector<const SystemSpec *> &specs, const std::vector<const double *> &B, int nB,
+                     const Opts &op, std::vector<FieldPlan> &plans) {
+  const int tot = (int)specs.size() * nB;
+  plans.assign(tot, FieldPlan());
+  std::vector<std::string> msgs(tot);
+  std::vector<char> ok(tot, 0);
+  const int nth = std::max(1, std::min<int>(tot, (int)std::thread::hardware_concurrency()));
+  std::vector<std::thread> th;
+  for (int t = 0; t < nth; ++t)
+    th.emplace_back([&, t]() {
+      for (int q = t; q < tot; q += nth)
+        ok[q] = plan_field(*specs[q / nB], B[q / nB][q % nB], op.tol, op.rdt, op.r_scale, op.chol_tol, op.max_growth,
+                           plans[q], msgs[q]);
+    });
+  for (auto &x : th) x.join();
+  for (int q = 0; q < tot; ++q)
+    if (!ok[q]) return fail(RP_EINVAL, "field " + std::to_string(q % nB) + ": " + msgs[q]);
   return RP_OK;
 }
 
+// Term kernel for a system: index pairs (complex FP32, at least 8 leading spin-1/2 nuclei),
+// the 256-index tile, or the generic mixed-radix form.
+template <typename R>
+static int term_kind_of(const SysArgs<R> &sa, const Opts &op) {
+  int kind = sa.tiled ? kTermTile : kTermGen;
+  if (std::is_same<R, float>::value && sa.tiled && sa.nhalf >= 8 && !(op.flags & RP_FLAG_TERM_SCALAR))
+    kind = kTermPair;
+  return kind;
+}
+
+// One system of a tiled propagation: spec in the internal axis order, its fields (host),
+// angles (device) and the index of its first output.
+struct TiledSys {
+  SystemSpec spec;
+  const double *B = nullptr;
+  const double *angles = nullptr;
+  int64_t out = 0;
+};
+
+// Tiled propagation of every (system, field, sample) job of a group of systems that share a
+// term kernel.  Jobs are ordered by decreasing step count, so the jobs still running at any
+// step form a prefix; consecutive jobs form chunks that fit the workspace and are propagated
+// together, one launch per Chebyshev term.  A chunk whose jobs all belong to one system uses
+// the kernels' uniform form (job = tile / nbx, system constants in the kernel arguments); a
+// chunk mixing systems of unequal Z uses the job queue (per-tile job index, per-job offsets,
+// per-system constants in a table).
+template <typename R>
+struct TiledRun {
+  struct Job {
+    int32_t sys, field, sample;
+  };
+  struct Chunk {
+    int64_t j0 = 0, nj = 0, sZ = 0, tiles = 0;
+    bool queue = false;
+  };
+  std::vector<TiledSys> sys;
+  int nB = 0;
+  int64_t M = 0;
+  int nt = 1, rcw = 8, rkp = 8, kind = kTermGen, remap = 0;
+  std::vector<FieldDev<R>> fdev;
+  std::vector<cx<R>> coef;
+  std::vector<R> ell;
+  std::vector<double> dts, sys_k;
+  std::vector<int64_t> nsteps, tab_off;
+  std::vector<SysArgs<R>> sargs;
+  int64_t tab_rows = 0;
+  std::vector<Job> jobs;
+  std::vector<Chunk> chunks;
+  int64_t max_nj = 0, max_sZ = 0, max_tiles = 0;
+  int64_t fixed_bytes = 0, chunk_bytes = 0;
+
+  int64_t Zof(const Job &j) const { return sys[j.sys].spec.Z; }
+  static int64_t nbx_of(int64_t Z) { return (Z + kBlock - 1) / kBlock; }
+  int64_t chunk_size(int64_t nj, int64_t sZ, int64_t tiles) const {
+    Sizer z;
+    for (int b = 0; b < 3; ++b) z.add<cx<R>>(4 * sZ);       // psi / phi_even, phi_odd, accumulator
+    z.add<cx<R>>((int64_t)nt * sZ);                          // singlet amplitudes of one step
+    z.add<double>(tiles);                                    // norm partials
+    z.add<double>(2 * tiles);                                // quadrature partials
+    z.add<int32_t>(tiles);                                   // tile -> job
+    z.add<double>(nj);                                       // phi
+    z.add<double>(nj);                                       // previous norm
+    z.add<int32_t>(nj);                                      // steps done
+    z.add<int32_t>(nj);                                      // field of each job
+    z.add<int32_t>(nj);                                      // sample of each job
+    z.add<int64_t>(nj);                                      // output index
+    z.add<QJob>(nj);
+    return z.used;
+  }
+
+  int prepare(const Opts &op, int64_t budget, bool default_chunks) {
+    const int ns = (int)sys.size();
+    std::vector<const SystemSpec *> specs;
+    std::vector<const double *> Bs;
+    for (auto &s : sys) {
+      specs.push_back(&s.spec);
+      Bs.push_back(s.B);
+    }
+    std::vector<FieldPlan> plans;
+    int rc = plan_many(specs, Bs, nB, op, plans);
+    if (rc) return rc;
+    int rk = 1;
+    for (auto &p : plans) {
+      nt = std::max(nt, p.n_terms);
+      rk = std::max(rk, p.rank);
+    }
+    // Pad the term count so that (nt - 2) is a multiple of 3: the accumulator is updated
+    // by the first launch (terms 0, 1) and then by every third launch (three terms each).
+    while ((nt - 2) % 3 != 0) ++nt;
+    // k_quad makes passes of rcw <= 64 (FP32) or 32 (FP64) columns, each reading every singlet
+    // amplitude once: the fewest passes that cover the rank, of equal width (a multiple of 8),
+    // with the rank padded by zero columns to passes * rcw.
+    const int wmax = sizeof(R) == 4 ? 64 : 32;
+    const int passes = (rk + wmax - 1) / wmax;
+    rcw = ((rk + passes - 1) / passes + 7) / 8 * 8;
+    rkp = passes * rcw;
+    const int nG = ns * nB;
+    fdev.assign(nG, FieldDev<R>());
+    coef.assign((size_t)nG * nt, cx<R>{R(0), R(0)});
+    ell.assign((size_t)nG * nt * rkp, R(0));
+    dts.assign(nG, 0.0);
+    nsteps.assign(nG, 0);
+    sargs.resize(ns);
+    sys_k.assign(2 * ns, 0.0);
+    tab_off.assign(ns, 0);
+    int64_t max_vec = 0;
+    for (int s = 0; s < ns; ++s) {
+      const SystemSpec &sp = sys[s].spec;
+      sargs[s] = make_sysargs<R>(sp);
+      sys_k[2 * s] = sp.kS;
+      sys_k[2 * s + 1] = std::min(sp.kS, sp.kT);
+      tab_off[s] = tab_rows;
+      tab_rows += M * std::max(sp.N(), 1);
+      max_vec = std::max<int64_t>(max_vec, 4 * sp.Z * (int64_t)sizeof(cx<R>));
+      const double dk = std::fabs(sp.kS - sp.kT);
+      for (int b = 0; b < nB; ++b) {
+        const int g = s * nB + b;
+        const FieldPlan &p = plans[g];
+        FieldDev<R> d;
+        d.omega = (R)p.omega;
+        d.c_re = (R)p.c_re;
+        d.c_im = (R)(p.c_im + (sp.kS >= sp.kT ? 0.0 : 0.5 * dk));
+        d.s1 = (R)(1.0 / p.r);
+        d.s2 = (R)(2.0 / p.r);
+        fdev[g] = d;
+        for (int n = 0; n < p.n_terms; ++n) coef[(size_t)g * nt + n] = {(R)p.coef[n].real(), (R)p.coef[n].imag()};
+        for (int n = 0; n < p.n_terms; ++n)
+          for (int r = 0; r < p.rank; ++r) ell[((size_t)g * nt + n) * rkp + r] = (R)p.ell[(size_t)n * p.rank + r];
+        dts[g] = p.dt;
+        nsteps[g] = p.n_steps;
+      }
+    }
+    // Jobs by decreasing step count (stable: system, field, sample order among equals).
+    jobs.clear();
+    for (int s = 0; s < ns; ++s)
+      for (int b = 0; b < nB; ++b)
+        for (int64_t m = 0; m < M; ++m) jobs.push_back({s, s * nB + b, (int32_t)m});
+    std::stable_sort(jobs.begin(), jobs.end(),
+                     [&](const Job &a, const Job &b) { return nsteps[a.field] > nsteps[b.field]; });
+    Sizer f;
+    f.add<FieldDev<R>>(nG);
+    f.add<cx<R>>((int64_t)coef.size());
+    f.add<R>((int64_t)ell.size());
+    f.add<double>(nG);
+    f.add<SysArgs<R>>(ns);
+    f.add<double>(2 * ns);
+    f.add<cx<double>>(tab_rows * (RP_MAX_TWO_I + 1));
+    fixed_bytes = f.used;
+    const int64_t region = budget - fixed_bytes;
+    // Chunks: consecutive jobs while the workspace allows; by default the chunk's three
+    // wavepacket buffers stay within 192 MB (resident in the 256 MB Infinity Cache across
+    // launches) unless that leaves fewer than 64 jobs; fewer than 2^24 workgroups per launch.
+    chunks.clear();
+    max_nj = max_sZ = max_tiles = 0;
+    const int64_t vec_cap = (int64_t)192 << 20;
+    Chunk c;
+    for (int64_t j = 0; j < (int64_t)jobs.size(); ++j) {
+      const int64_t Z = Zof(jobs[j]), nbx = nbx_of(Z);
+      const int64_t nj = c.nj + 1, sZ = c.sZ + Z, tiles = c.tiles + nbx;
+      bool fits = chunk_size(std::max(max_nj, nj), std::max(max_sZ, sZ), std::max(max_tiles, tiles)) <= region &&
+                  tiles < ((int64_t)1 << 24);
+      if (default_chunks && c.nj >= 64 && 3 * 4 * sZ * (int64_t)sizeof(cx<R>) > vec_cap) fits = false;
+      if (!fits && c.nj == 0)
+        return fail(RP_ENOMEM, "workspace of " + std::to_string(budget) + " bytes is too small for one wavepacket of " +
+                                   std::to_string(Z) + " nuclear states (needs " +
+                                   std::to_string(fixed_bytes + chunk_size(1, Z, nbx)) + ")");
+      if (!fits) {
+        chunks.push_back(c);
+        max_nj = std::max(max_nj, c.nj);
+        max_sZ = std::max(max_sZ, c.sZ);
+        max_tiles = std::max(max_tiles, c.tiles);
+        c = Chunk();
+        c.j0 = j;
+        --j;
+        continue;
+      }
+      c.nj = nj;
+      c.sZ = sZ;
+      c.tiles = tiles;
+    }
+    if (c.nj) {
+      chunks.push_back(c);
+      max_nj = std::max(max_nj, c.nj);
+      max_sZ = std::max(max_sZ, c.sZ);
+      max_tiles = std::max(max_tiles, c.tiles);
+    }
+    for (auto &ch : chunks) {
+      ch.queue = false;
+      for (int64_t j = ch.j0 + 1; j < ch.j0 + ch.nj; ++j)
+        if (jobs[j].sys != jobs[ch.j0].sys) ch.queue = true;
+    }
+    chunk_bytes = chunk_size(max_nj, max_sZ, max_tiles);
+    // Block order: a wavepacket that fits an XCD's 4 MB L2 comfortably is given to one XCD
+    // (its partner tiles stay in that L2); larger ones are spread over all XCDs, so that the
+    // whole GPU works on few wavepackets at a time and far partners hit the Infinity Cache.
+    remap = max_vec <= ((int64_t)1 << 20) ? 1 : 0;
+    if (op.flags & RP_FLAG_XCD_LOCAL) remap = 1;
+    if (op.flags & RP_FLAG_XCD_SPREAD) remap = 0;
+    return RP_OK;
+  }
+
+  int run(Arena &ar, const Opts &op, double *phi_out, double *ps_out, int *flag, bool use_graph, hipStream_t st,
+          EventLog &log) {
+    const int ns = (int)sys.size();
+    const int nG = ns * nB;
+    FieldDev<R> *dF = ar.take<FieldDev<R>>(nG);
+    cx<R> *dCoef = ar.take<cx<R>>((int64_t)coef.size());
+    R *dEll = ar.take<R>((int64_t)ell.size());
+    double *dDt = ar.take<double>(nG);
+    SysArgs<R> *dSys = ar.take<SysArgs<R>>(ns);
+    double *dK = ar.take<double>(2 * ns);
+    cx<double> *dTab = ar.take<cx<double>>(tab_rows * (RP_MAX_TWO_I + 1));
+    cx<R> *bufs[3];
+    for (int b = 0; b < 3; ++b) bufs[b] = ar.take<cx<R>>(4 * max_sZ);
+    cx<R> *D = ar.take<cx<R>>((int64_t)nt * max_sZ);
+    double *dPn = ar.take<double>(max_tiles);
+    double *dPq = ar.take<double>(2 * max_tiles);
+    int32_t *dTileJob = ar.take<int32_t>(max_tiles);
+    double *dPhi = ar.take<double>(max_nj);
+    double *dPrev = ar.take<double>(max_nj);
+    int32_t *dStep = ar.take<int32_t>(max_nj);
+    int32_t *dJf = ar.take<int32_t>(max_nj);
+    int32_t *dJs = ar.take<int32_t>(max_nj);
+    int64_t *dDst = ar.take<int64_t>(max_nj);
+    QJob *dJobs = ar.take<QJob>(max_nj);
+    if (ar.overflow) return fail(RP_ENOMEM, "internal: workspace layout overflow");
+    HIPCHK(hipMemcpyAsync(dF, fdev.data(), nG * sizeof(FieldDev<R>), hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(dCoef, coef.data(), coef.size() * sizeof(cx<R>), hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(dEll, ell.data(), ell.size() * sizeof(R), hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(dDt, dts.data(), nG * 8, hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(dSys, sargs.data(), ns * sizeof(SysArgs<R>), hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(dK, sys_k.data(), 2 * ns * 8, hipMemcpyHostToDevice, st));
+    for (int s = 0; s < ns; ++s) {
+      const SystemSpec &sp = sys[s].spec;
+      if (ps_out) {   // time points past a field's last step stay NaN
+        const int64_t n = (int64_t)nB * M * op.ps_len;
+        hipLaunchKernelGGL(k_fill, dim3(grid1(n)), dim3(256), 0, st, ps_out + sys[s].out * op.ps_len, n, std::nan(""));
+        HIPCHK(hipGetLastError());
+      }
+      // Coherent-state components of every sample (shared by all fields).
+      const int N = sp.N();
+      if (N > 0 && M > 0) {
+        CohArgs ca;
+        std::memset(&ca, 0, sizeof(ca));
+        ca.angles = sys[s].angles;
+        ca.tab = dTab + tab_off[s] * (RP_MAX_TWO_I + 1);
+        ca.M = M;
+        ca.N = N;
+        ca.mode = op.init_mode;
+        for (int k = 0; k < N; ++k) {
+          ca.two_I[k] = sp.two_I[k];
+          ca.perm[k] = sp.perm[k];
+        }
+        hipLaunchKernelGGL(k_coherent, dim3(grid1(M * N)), dim3(256), 0, st, ca);
+        HIPCHK(hipGetLastError());
+      }
+    }
+    const double rtol = op.precision == 64 ? 1e-9 : 1e-4;
+    std::vector<int32_t> hJf, hJs, hTile;
+    std::vector<int64_t> hDst, tile_start;
+    std::vector<QJob> hJobs;
+    for (const Chunk &ch : chunks) {
+      const int64_t nj = ch.nj;
+      const int s0 = jobs[ch.j0].sys;
+      const SystemSpec &sp0 = sys[s0].spec;
+      // Streaming (non-temporal) loads and stores of phi_{n-1}, phi_{n+1} and the accumulator
+      // when the chunk's three wavepacket buffers exceed the 256 MB Infinity Cache: they would
+      // not survive there until the next launch anyway, and the hint leaves the L2 to the
+      // partner tiles of phi_n.  The singlet amplitudes, read only by the quadrature, always
+      // stream.
+      const bool stream_nt = 3 * 4 * ch.sZ * (int64_t)sizeof(cx<R>) > ((int64_t)256 << 20);
+      hJf.assign(nj, 0);
+      hJs.assign(nj, 0);
+      hDst.assign(nj, 0);
+      hJobs.assign(nj, QJob());
+      tile_start.assign(nj + 1, 0);
+      hTile.clear();
+      int64_t vec = 0, amp = 0;
+      for (int64_t q = 0; q < nj; ++q) {
+        const Job &jb = jobs[ch.j0 + q];
+        const SystemSpec &sp = sys[jb.sys].spec;
+        const int64_t Z = sp.Z, nbx = nbx_of(Z);
+        hJf[q] = jb.field;
+        hJs[q] = jb.sample;
+        hDst[q] = sys[jb.sys].out + (int64_t)(jb.field - jb.sys * nB) * M + jb.sample;
+        QJob &qj = hJobs[q];
+        qj.sys = jb.sys;
+        qj.field = jb.field;
+        qj.nbx = (int32_t)nbx;
+        qj.pad = 0;
+        qj.Z = Z;
+        qj.vec = vec;
+        qj.amp = amp;
+        qj.blk = tile_start[q];
+        qj.tab = tab_off[jb.sys] + (int64_t)jb.sample * std::max(sp.N(), 1);
+        tile_start[q + 1] = tile_start[q] + nbx;
+        vec += 4 * Z;
+        amp += Z;
+        if (ch.queue)
+          for (int64_t b = 0; b < nbx; ++b) hTile.push_back((int32_t)q);
+      }
+      HIPCHK(hipMemcpyAsync(dJf, hJf.data(), nj * 4, hipMemcpyHostToDevice, st));
+      HIPCHK(hipMemcpyAsync(dJs, hJs.data(), nj * 4, hipMemcpyHostToDevice, st));
+      HIPCHK(hipMemcpyAsync(dDst, hDst.data(), nj * 8, hipMemcpyHostToDevice, st));
+      HIPCHK(hipMemcpyAsync(dJobs, hJobs.data(), nj * sizeof(QJob), hipMemcpyHostToDevice, st));
+      if (ch.queue) HIPCHK(hipMemcpyAsync(dTileJob, hTile.data(), hTile.size() * 4, hipMemcpyHostToDevice, st));
+      const int64_t nbx0 = nbx_of(sp0.Z);
+      const SysArgs<R> &sa0 = sargs[s0];
+      // initial wavepackets
+      {
+        InitArgs<R> ia;
+        std::memset(&ia, 0, sizeof(ia));
+        ia.psi = bufs[0];
+        ia.tab = ch.queue ? dTab : dTab + tab_off[s0] * (RP_MAX_TWO_I + 1);
+        ia.job_sample = dJs;
+        ia.tile_job = dTileJob;
+        ia.jobs = dJobs;
+        ia.systab = dSys;
+        ia.Z = sp0.Z;
+        ia.nbx = nbx0;
+        ia.tiles = ch.tiles;
+        ia.njobs = (int32_t)nj;
+        ia.N = sp0.N();
+        for (int k = 0; k < sp0.N(); ++k) {
+          ia.stride[k] = sa0.stride[k];
+          ia.d[k] = sa0.d[k];
+        }
+        if (sp0.N() == 0) {
+          ia.stride[0] = 1;
+          ia.d[0] = 1;
+        }
+        if (ch.queue)
+          hipLaunchKernelGGL((k_init<R, true>), dim3((unsigned)ch.tiles), dim3(kBlock), 0, st, ia);
+        else
+          hipLaunchKernelGGL((k_init<R, false>), dim3((unsigned)ch.tiles), dim3(kBlock), 0, st, ia);
+        HIPCHK(hipGetLastError());
+      }
+      hipLaunchKernelGGL(k_fill, dim3(grid1(nj)), dim3(256), 0, st, dPhi, nj, 0.0);
+      hipLaunchKernelGGL(k_fill, dim3(grid1(nj)), dim3(256), 0, st, dPrev, nj, 1.0 + 1e-6);
+      hipLaunchKernelGGL(k_fill_i32, dim3(grid1(nj)), dim3(256), 0, st, dStep, nj, 0);
+      HIPCHK(hipGetLastError());
+      int ip = 0, ia_ = 2, iodd = 1;   // psi, accumulator and odd-term buffers
+      const int64_t slab = ch.sZ;
+      // All launches of one step: Chebyshev terms, in-step quadrature, finalisation.
+      auto enqueue_step = [&](int64_t active, int ipsi, int iacc) {
+        const int64_t tiles = tile_start[active];
+        const unsigned grid = (unsigned)tiles;
+        TermArgs<R> ta;
+        std::memset(&ta, 0, sizeof(ta));
+        ta.fields = dF;
+        ta.coef = dCoef;
+        ta.job_field = dJf;
+        ta.part_norm = dPn;
+        ta.tile_job = dTileJob;
+        ta.jobs = dJobs;
+        ta.systab = dSys;
+        ta.nbx = nbx0;
+        ta.tiles = tiles;
+        ta.njobs = (int32_t)active;
+        ta.n_terms = nt;
+        ta.remap = remap;
+        ta.acc = bufs[iacc];
+        cx<R> *even = bufs[ipsi], *odd = bufs[iodd];
+        // n = 0: phi_1 = Gh phi_0
+        ta.phin = even;
+        ta.phio = odd;
+        ta.n = 0;
+        ta.dnext = D + slab;
+        ta.dfirst = D;
+        const double eb = (double)sizeof(R) / 4.0;   // bytes per element, in units of complex-FP32 bytes
+        log.mark(st);
+        launch_term<R>(kFirst, kind, stream_nt, ch.queue, grid, st, ta, sa0);
+        double bytes = 28.0 * eb;
+        for (int n = 1; n + 1 < nt; ++n) {
+          // phi_{n+1} = 2 Gh phi_n - phi_{n-1}, written over phi_{n-1}; every third launch also
+          // adds phi_{n-1}, phi_n, phi_{n+1} to the step accumulator.
+          ta.phin = (n & 1) ? odd : even;
+          ta.phio = (n & 1) ? even : odd;
+          ta.n = n;
+          ta.dnext = D + (int64_t)(n + 1) * slab;
+          const bool acc3 = (n % 3) == 0;
+          launch_term<R>(acc3 ? kAcc3 : kPlain, kind, stream_nt, ch.queue, grid, st, ta, sa0);
+          bytes += (acc3 ? 42.0 : 26.0) * eb;
+        }
+        log.mark(st);
+        log.close(0);
+        if (log.on) {
+          int64_t el = 0;   // wavepacket elements of the launch
+          for (int64_t q = 0; q < active; ++q) el += 4 * hJobs[q].Z;
+          g_prof.term_launches += nt - 1;
+          g_prof.elems += (double)(nt - 1) * (double)el;
+          g_prof.bytes += bytes * (double)el;
+          g_prof.quad_launches += 1;
+          g_prof.terms = nt;
+        }
+        QuadArgs<R> qa;
+        std::memset(&qa, 0, sizeof(qa));
+        qa.d = D;
+        qa.slab = slab;
+        qa.ell = dEll;
+        qa.job_field = dJf;
+        qa.part = dPq;
+        qa.tile_job = dTileJob;
+        qa.jobs = dJobs;
+        qa.Z = sp0.Z;
+        qa.nbx = nbx0;
+        qa.tiles = tiles;
+        qa.njobs = (int32_t)active;
+        qa.n_terms = nt;
+        qa.rank_pad = rkp;
+        qa.remap = remap;
+        log.mark(st);
+        launch_quad<R>(rcw, ch.queue, grid, st, qa);
+        log.mark(st);
+        log.close(1);
+        FinArgs fa;
+        std::memset(&fa, 0, sizeof(fa));
+        fa.part_q = dPq;
+        fa.part_norm = dPn;
+        fa.phi = dPhi;
+        fa.prev_norm = dPrev;
+        fa.flag = flag;
+        fa.job_field = dJf;
+        fa.dt = dDt;
+        fa.stepc = dStep;
+        fa.jobs = ch.queue ? dJobs : nullptr;
+        fa.sys_k = dK;
+        fa.nbx = nbx0;
+        fa.njobs = (int32_t)active;
+        fa.kS = sp0.kS;
+        fa.kmin = std::min(sp0.kS, sp0.kT);
+        fa.rtol = rtol;
+        fa.ps_t = ps_out;
+        fa.dst = dDst;
+        fa.ps_len = op.ps_len;
+        hipLaunchKernelGGL(k_finalize, dim3((unsigned)active), dim3(kBlock), 0, st, fa);
+      };
+      // One captured graph per (active jobs, buffer parity) of this chunk, replayed every step.
+      using GraphKey = std::pair<int64_t, int>;
+      std::map<GraphKey, hipGraphExec_t> graphs;
+      // HIP does not promise that destroying an executable graph waits for its launches, so the
+      // chunk's launches are waited for before its graphs are destroyed.
+      struct GraphsGuard {
+        std::map<GraphKey, hipGraphExec_t> &g;
+        hipStream_t s;
+        ~GraphsGuard() {
+          if (g.empty()) return;
+          (void)hipStreamSynchronize(s);
+          for (auto &kv : g) (void)hipGraphExecDestroy(kv.second);
+        }
+      } graphs_guard{graphs, st};
+      const int64_t steps_max = nsteps[jobs[ch.j0].field];
+      int64_t active = nj;
+      for (int64_t t = 0; t < steps_max; ++t) {
+        // Jobs with more than t steps form a prefix of the chunk.
+        while (active > 0 && nsteps[jobs[ch.j0 + active - 1].field] <= t) --active;
+        if (active <= 0) break;
+        if (use_graph) {
+          const GraphKey key{active, ip};
+          auto it = graphs.find(key);
+          if (it == graphs.end()) {
+            HIPCHK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+            enqueue_step(active, ip, ia_);
+            hipGraph_t g = nullptr;
+            const hipError_t ec = hipStreamEndCapture(st, &g);
+            if (ec != hipSuccess || !g) return fail(RP_EDEVICE, std::string("graph capture: ") + hipGetErrorString(ec));
+            hipGraphExec_t ge = nullptr;
+            const hipError_t ei = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(g);
+            if (ei != hipSuccess) return fail(RP_EDEVICE, std::string("graph instantiate: ") + hipGetErrorString(ei));
+            it = graphs.emplace(key, ge).first;
+          }
+          HIPCHK(hipGraphLaunch(it->second, st));
+        } else {
+          enqueue_step(active, ip, ia_);
+          HIPCHK(hipGetLastError());
+        }
+        std::swap(ip, ia_);
+      }
+      hipLaunchKernelGGL(k_scatter, dim3(grid1(nj)), dim3(256), 0, st, (const double *)dPhi, (const int64_t *)dDst,
+                         phi_out, nj);
+      HIPCHK(hipGetLastError());
+    }
+    return RP_OK;
+  }
+};
 
 // Quadrature columns the resident kernel keeps per thread: 32 up to 512-thread workgroups, 24 for
 // 1024 threads (register budget 128 per lane).
 static int res_rank_limit(int64_t Z) { return Z > 512 ? 24 : kResRank; }
 
-// Propagates all jobs of the LDS-resident systems `idx` (one launch per block-size class).
+// Every job of the LDS-resident systems of a call (one launch per workgroup-size class).
 template <typename R>
-static int propagate_resident(const std::vector<int> &idx, const rp_system *sys, const double *B_mT, int nB,
-                              const double *angles, const std::vector<int64_t> &aoff, int64_t M, const Opts &op,
-                              double *phi, hipStream_t st) {
-  const int ns = (int)idx.size();
+struct ResidentRun {
   std::vector<SystemSpec> specs;
-  for (int i : idx)
-    specs.push_back(tile_order(make_spec(sys[i].n_nuc[0], sys[i].n_nuc[1], sys[i].two_I, sys[i].a_mT, sys[i].J_mT,
-                                         sys[i].kS, sys[i].kT, sys[i].T_us, gamma_of(&sys[i]))));
-  // Plan every (system, field) with a step short enough that the quadrature rank fits kResRank.
-  std::vector<FieldPlan> plans((size_t)ns * nB);
-  std::vector<std::string> msgs((size_t)ns * nB);
-  std::vector<char> ok((size_t)ns * nB, 0);
-  {
-    const int tot = ns * nB;
-    const int nth = std::max(1, std::min<int>(tot, (int)std::thread::hardware_concurrency()));
-    std::vector<std::thread> th;
-    for (int t = 0; t < nth; ++t)
-      th.emplace_back([&, t]() {
-        for (int q = t; q < tot; q += nth) {
-          const int i = q / nB, b = q % nB;
-          const int rmax = res_rank_limit(specs[i].Z);
-          double rdt = std::min(op.rdt, 40.0);
-          for (int tries = 0; tries < 12; ++tries) {
-            ok[q] = plan_field(specs[i], B_mT[(int64_t)idx[i] * nB + b], op.tol, rdt, op.r_scale, op.chol_tol,
-                               op.max_growth, plans[q], msgs[q]);
-            if (!ok[q] || plans[q].rank <= rmax) break;
-            rdt *= 0.75;
-          }
-          if (ok[q] && plans[q].rank > rmax) {
-            ok[q] = 0;
-            msgs[q] = "quadrature rank does not fit the resident kernel";
-          }
-        }
-      });
-    for (auto &x : th) x.join();
-  }
-  for (size_t q = 0; q < plans.size(); ++q)
-    if (!ok[q]) return fail(RP_EINVAL, "field plan: " + msgs[q]);
-  // Descriptors.
-  std::vector<ResSys<R>> rsys(ns);
-  std::vector<ResField<R>> rf((size_t)ns * nB);
+  std::vector<const double *> B, angles;
+  std::vector<int64_t> out;          // index of each system's first output
+  int nB = 0;
+  int64_t M = 0;
+  std::vector<ResSys<R>> rsys;
+  std::vector<ResField<R>> rf;
   std::vector<cx<R>> coef;
   std::vector<R> ell;
+  std::vector<ResJob> all;
+  std::vector<int64_t> start;
   int64_t tab_elems = 0;
-  const double rtol = op.precision == 64 ? 1e-9 : 1e-4;
-  for (int i = 0; i < ns; ++i) {
-    std::memset(&rsys[i], 0, sizeof(ResSys<R>));
-    rsys[i].sa = make_sysargs<R>(specs[i]);
-    rsys[i].tab_off = tab_elems;
-    rsys[i].kS = specs[i].kS;
-    rsys[i].kmin = std::min(specs[i].kS, specs[i].kT);
-    rsys[i].rtol = rtol;
-    tab_elems += M * std::max(specs[i].N(), 1) * (RP_MAX_TWO_I + 1);
-    const double dk = std::fabs(specs[i].kS - specs[i].kT);
-    for (int b = 0; b < nB; ++b) {
-      const FieldPlan &p = plans[(size_t)i * nB + b];
-      ResField<R> &f = rf[(size_t)i * nB + b];
-      std::memset(&f, 0, sizeof(f));
-      f.fd.omega = (R)p.omega;
-      f.fd.c_re = (R)p.c_re;
-      f.fd.c_im = (R)(p.c_im + (specs[i].kS >= specs[i].kT ? 0.0 : 0.5 * dk));
-      f.fd.s1 = (R)(1.0 / p.r);
-      f.fd.s2 = (R)(2.0 / p.r);
-      f.dt = p.dt;
-      f.n_steps = (int32_t)p.n_steps;
-      f.n_terms = p.n_terms;
-      f.coef_off = (int64_t)coef.size();
-      for (int n = 0; n < p.n_terms; ++n) coef.push_back({(R)p.coef[n].real(), (R)p.coef[n].imag()});
-      f.ell_off = (int64_t)ell.size();
-      for (int n = 0; n < p.n_terms; ++n)
-        for (int r = 0; r < kResRank; ++r) ell.push_back(r < p.rank ? (R)p.ell[(size_t)n * p.rank + r] : R(0));
+  int64_t bytes = 0;
+
+  int prepare(const Opts &op) {
+    const int ns = (int)specs.size();
+    // Plan every (system, field) with a step short enough that the quadrature rank fits kResRank.
+    std::vector<FieldPlan> plans((size_t)ns * nB);
+    std::vector<std::string> msgs((size_t)ns * nB);
+    std::vector<char> ok((size_t)ns * nB, 0);
+    {
+      const int tot = ns * nB;
+      const int nth = std::max(1, std::min<int>(tot, (int)std::thread::hardware_concurrency()));
+      std::vector<std::thread> th;
+      for (int t = 0; t < nth; ++t)
+        th.emplace_back([&, t]() {
+          for (int q = t; q < tot; q += nth) {
+            const int i = q / nB, b = q % nB;
+            const int rmax = res_rank_limit(specs[i].Z);
+            double rdt = std::min(op.rdt, 40.0);
+            for (int tries = 0; tries < 12; ++tries) {
+              ok[q] = plan_field(specs[i], B[i][b], op.tol, rdt, op.r_scale, op.chol_tol, op.max_growth, plans[q],
+                                 msgs[q]);
+              if (!ok[q] || plans[q].rank <= rmax) break;
+              rdt *= 0.75;
+            }
+            if (ok[q] && plans[q].rank > rmax) {
+              ok[q] = 0;
+              msgs[q] = "quadrature rank does not fit the resident kernel";
+            }
+          }
+        });
+      for (auto &x : th) x.join();
     }
-  }
-  // Jobs grouped by workgroup size (next power of two >= max(64, Z)), longest first.
-  std::vector<std::vector<ResJob>> groups(5);   // 64, 128, 256, 512, 1024
-  std::vector<std::vector<double>> costs(5);
-  for (int i = 0; i < ns; ++i) {
-    int g = 0;
-    while ((64 << g) < specs[i].Z) ++g;
-    for (int b = 0; b < nB; ++b) {
-      const FieldPlan &p = plans[(size_t)i * nB + b];
-      for (int64_t s = 0; s < M; ++s) {
-        ResJob j;
-        j.sys = i;
-        j.field = i * nB + b;
-        j.sample = (int32_t)s;
-        j.pad = 0;
-        j.out = ((int64_t)idx[i] * nB + b) * M + s;
-        groups[g].push_back(j);
-        costs[g].push_back((double)p.n_steps * p.n_terms);
+    for (size_t q = 0; q < plans.size(); ++q)
+      if (!ok[q]) return fail(RP_EINVAL, "field plan: " + msgs[q]);
+    rsys.assign(ns, ResSys<R>());
+    rf.assign((size_t)ns * nB, ResField<R>());
+    coef.clear();
+    ell.clear();
+    tab_elems = 0;
+    const double rtol = op.precision == 64 ? 1e-9 : 1e-4;
+    for (int i = 0; i < ns; ++i) {
+      std::memset(&rsys[i], 0, sizeof(ResSys<R>));
+      rsys[i].sa = make_sysargs<R>(specs[i]);
+      rsys[i].tab_off = tab_elems;
+      rsys[i].kS = specs[i].kS;
+      rsys[i].kmin = std::min(specs[i].kS, specs[i].kT);
+      rsys[i].rtol = rtol;
+      tab_elems += M * std::max(specs[i].N(), 1) * (RP_MAX_TWO_I + 1);
+      const double dk = std::fabs(specs[i].kS - specs[i].kT);
+      for (int b = 0; b < nB; ++b) {
+        const FieldPlan &p = plans[(size_t)i * nB + b];
+        ResField<R> &f = rf[(size_t)i * nB + b];
+        std::memset(&f, 0, sizeof(f));
+        f.fd.omega = (R)p.omega;
+        f.fd.c_re = (R)p.c_re;
+        f.fd.c_im = (R)(p.c_im + (specs[i].kS >= specs[i].kT ? 0.0 : 0.5 * dk));
+        f.fd.s1 = (R)(1.0 / p.r);
+        f.fd.s2 = (R)(2.0 / p.r);
+        f.dt = p.dt;
+        f.n_steps = (int32_t)p.n_steps;
+        f.n_terms = p.n_terms;
+        f.coef_off = (int64_t)coef.size();
+        for (int n = 0; n < p.n_terms; ++n) coef.push_back({(R)p.coef[n].real(), (R)p.coef[n].imag()});
+        f.ell_off = (int64_t)ell.size();
+        for (int n = 0; n < p.n_terms; ++n)
+          for (int r = 0; r < kResRank; ++r) ell.push_back(r < p.rank ? (R)p.ell[(size_t)n * p.rank + r] : R(0));
       }
     }
-  }
-  struct Buf {
-    void *p = nullptr;
-    ~Buf() { if (p) (void)hipFree(p); }
-  };
-  Buf bS, bF, bC, bE, bT, bJ, bFl;
-  auto alloc = [&](Buf &b, size_t n) -> int {
-    if (hipMalloc(&b.p, std::max<size_t>(n, 16)) != hipSuccess) {
-      (void)hipGetLastError();
-      return fail(RP_ENOMEM, "hipMalloc failed");
+    // Jobs grouped by workgroup size (next power of two >= max(64, Z)), longest first.
+    std::vector<std::vector<ResJob>> groups(5);   // 64, 128, 256, 512, 1024
+    std::vector<std::vector<double>> costs(5);
+    for (int i = 0; i < ns; ++i) {
+      int g = 0;
+      while ((64 << g) < specs[i].Z) ++g;
+      for (int b = 0; b < nB; ++b) {
+        const FieldPlan &p = plans[(size_t)i * nB + b];
+        for (int64_t s = 0; s < M; ++s) {
+          ResJob j;
+          j.sys = i;
+          j.field = i * nB + b;
+          j.sample = (int32_t)s;
+          j.pad = 0;
+          j.out = out[i] + (int64_t)b * M + s;
+          groups[g].push_back(j);
+          costs[g].push_back((double)p.n_steps * p.n_terms);
+        }
+      }
     }
+    all.clear();
+    start.assign(6, 0);
+    for (int g = 0; g < 5; ++g) {
+      std::vector<size_t> ord(groups[g].size());
+      std::iota(ord.begin(), ord.end(), 0);
+      std::stable_sort(ord.begin(), ord.end(), [&](size_t a, size_t b) { return costs[g][a] > costs[g][b]; });
+      for (size_t q : ord) all.push_back(groups[g][q]);
+      start[g + 1] = (int64_t)all.size();
+    }
+    Sizer z;
+    z.add<ResSys<R>>(ns);
+    z.add<ResField<R>>((int64_t)rf.size());
+    z.add<cx<R>>((int64_t)coef.size());
+    z.add<R>((int64_t)ell.size());
+    z.add<cx<double>>(tab_elems);
+    z.add<ResJob>((int64_t)all.size());
+    bytes = z.used;
     return RP_OK;
-  };
-  int64_t njobs = 0;
-  for (auto &g : groups) njobs += (int64_t)g.size();
-  int rc;
-  if ((rc = alloc(bS, rsys.size() * sizeof(ResSys<R>))) || (rc = alloc(bF, rf.size() * sizeof(ResField<R>))) ||
-      (rc = alloc(bC, coef.size() * sizeof(cx<R>))) || (rc = alloc(bE, ell.size() * sizeof(R))) ||
-      (rc = alloc(bT, tab_elems * sizeof(cx<double>))) || (rc = alloc(bJ, njobs * sizeof(ResJob))) ||
-      (rc = alloc(bFl, 16)))
-    return rc;
-  HIPCHK(hipMemcpyAsync(bS.p, rsys.data(), rsys.size() * sizeof(ResSys<R>), hipMemcpyHostToDevice, st));
-  HIPCHK(hipMemcpyAsync(bF.p, rf.data(), rf.size() * sizeof(ResField<R>), hipMemcpyHostToDevice, st));
-  HIPCHK(hipMemcpyAsync(bC.p, coef.data(), coef.size() * sizeof(cx<R>), hipMemcpyHostToDevice, st));
-  HIPCHK(hipMemcpyAsync(bE.p, ell.data(), ell.size() * sizeof(R), hipMemcpyHostToDevice, st));
-  HIPCHK(hipMemsetAsync(bFl.p, 0, 16, st));
-  for (int i = 0; i < ns; ++i) {
-    const int N = specs[i].N();
-    CohArgs ca;
-    std::memset(&ca, 0, sizeof(ca));
-    ca.angles = angles + aoff[idx[i]];
-    ca.tab = (cx<double> *)bT.p + rsys[i].tab_off;
-    ca.M = M;
-    ca.N = N;
-    ca.mode = op.init_mode;
-    for (int k = 0; k < N; ++k) {
-      ca.two_I[k] = specs[i].two_I[k];
-      ca.perm[k] = specs[i].perm[k];
-    }
-    if (N > 0) hipLaunchKernelGGL(k_coherent, dim3(grid1(M * N)), dim3(256), 0, st, ca);
   }
-  HIPCHK(hipGetLastError());
-  std::vector<ResJob> all;
-  std::vector<int64_t> start(6, 0);
-  for (int g = 0; g < 5; ++g) {
-    std::vector<size_t> ord(groups[g].size());
-    std::iota(ord.begin(), ord.end(), 0);
-    std::stable_sort(ord.begin(), ord.end(), [&](size_t a, size_t b) { return costs[g][a] > costs[g][b]; });
-    for (size_t q : ord) all.push_back(groups[g][q]);
-    start[g + 1] = (int64_t)all.size();
-  }
-  HIPCHK(hipMemcpyAsync(bJ.p, all.data(), all.size() * sizeof(ResJob), hipMemcpyHostToDevice, st));
-  for (int g = 0; g < 5; ++g) {
-    const int64_t n = start[g + 1] - start[g];
-    if (n == 0) continue;
-    const int Zb = 64 << g;
-    ResArgs<R> ra;
-    ra.sys = (const ResSys<R> *)bS.p;
-    ra.fields = (const ResField<R> *)bF.p;
-    ra.jobs = (const ResJob *)bJ.p + start[g];
-    ra.coef = (const cx<R> *)bC.p;
-    ra.ell = (const R *)bE.p;
-    ra.tab = (const cx<double> *)bT.p;
-    ra.phi = phi;
-    ra.flag = (int *)bFl.p;
-    ra.njobs = n;
-    const size_t shmem = 2 * 4 * (size_t)Zb * sizeof(cx<R>);
-    if (Zb > 512) {
-      HIPCHK(hipFuncSetAttribute((const void *)k_resident<R, 1024, 24>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                 (int)shmem));
-      hipLaunchKernelGGL((k_resident<R, 1024, 24>), dim3((unsigned)n), dim3(Zb), shmem, st, ra);
-    } else {
-      HIPCHK(hipFuncSetAttribute((const void *)k_resident<R, 512, kResRank>,
-                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem));
-      hipLaunchKernelGGL((k_resident<R, 512, kResRank>), dim3((unsigned)n), dim3(Zb), shmem, st, ra);
+
+  int run(Arena &ar, const Opts &op, double *phi, int *flag, hipStream_t st) {
+    const int ns = (int)specs.size();
+    ResSys<R> *dS = ar.take<ResSys<R>>(ns);
+    ResField<R> *dF = ar.take<ResField<R>>((int64_t)rf.size());
+    cx<R> *dC = ar.take<cx<R>>((int64_t)coef.size());
+    R *dE = ar.take<R>((int64_t)ell.size());
+    cx<double> *dT = ar.take<cx<double>>(tab_elems);
+    ResJob *dJ = ar.take<ResJob>((int64_t)all.size());
+    if (ar.overflow) return fail(RP_ENOMEM, "internal: workspace layout overflow");
+    HIPCHK(hipMemcpyAsync(dS, rsys.data(), rsys.size() * sizeof(ResSys<R>), hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(dF, rf.data(), rf.size() * sizeof(ResField<R>), hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(dC, coef.data(), coef.size() * sizeof(cx<R>), hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(dE, ell.data(), ell.size() * sizeof(R), hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(dJ, all.data(), all.size() * sizeof(ResJob), hipMemcpyHostToDevice, st));
+    for (int i = 0; i < ns; ++i) {
+      const int N = specs[i].N();
+      CohArgs ca;
+      std::memset(&ca, 0, sizeof(ca));
+      ca.angles = angles[i];
+      ca.tab = dT + rsys[i].tab_off;
+      ca.M = M;
+      ca.N = N;
+      ca.mode = op.init_mode;
+      for (int k = 0; k < N; ++k) {
+        ca.two_I[k] = specs[i].two_I[k];
+        ca.perm[k] = specs[i].perm[k];
+      }
+      if (N > 0) hipLaunchKernelGGL(k_coherent, dim3(grid1(M * N)), dim3(256), 0, st, ca);
     }
     HIPCHK(hipGetLastError());
+    for (int g = 0; g < 5; ++g) {
+      const int64_t n = start[g + 1] - start[g];
+      if (n == 0) continue;
+      const int Zb = 64 << g;
+      ResArgs<R> ra;
+      ra.sys = dS;
+      ra.fields = dF;
+      ra.jobs = dJ + start[g];
+      ra.coef = dC;
+      ra.ell = dE;
+      ra.tab = dT;
+      ra.phi = phi;
+      ra.flag = flag;
+      ra.njobs = n;
+      const size_t shmem = 2 * 4 * (size_t)Zb * sizeof(cx<R>);
+      if (Zb > 512) {
+        HIPCHK(hipFuncSetAttribute((const void *)k_resident<R, 1024, 24>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                   (int)shmem));
+        hipLaunchKernelGGL((k_resident<R, 1024, 24>), dim3((unsigned)n), dim3(Zb), shmem, st, ra);
+      } else {
+        HIPCHK(hipFuncSetAttribute((const void *)k_resident<R, 512, kResRank>,
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem));
+        hipLaunchKernelGGL((k_resident<R, 512, kResRank>), dim3((unsigned)n), dim3(Zb), shmem, st, ra);
+      }
+      HIPCHK(hipGetLastError());
+    }
+    return RP_OK;
   }
-  int flag = 0;
-  HIPCHK(hipMemcpyAsync(&flag, bFl.p, sizeof(int), hipMemcpyDeviceToHost, st));
+};
+
+// The Chebyshev path of rp_propagate (and of its variant on the static scratch area): plans
+// every system, sizes one workspace for the call, then runs the LDS-resident systems and the
+// tiled groups one after another on the caller's stream (each part reuses the same workspace:
+// stream order separates them).  scratch: device memory of scratch_bytes to use instead of an
+// allocation (nullptr: one stream-ordered allocation for the call).
+template <typename R>
+static int propagate_chebyshev(const rp_system *sys, int n_sys, const double *B_mT, int nB, const double *angles,
+                               int64_t M, const Opts &op, double *phi, double *ps_t, hipStream_t st, EventLog &log,
+                               char *scratch, int64_t scratch_bytes) {
+  std::vector<int64_t> aoffs(n_sys, 0);
+  {
+    int64_t o = 0;
+    for (int i = 0; i < n_sys; ++i) {
+      aoffs[i] = o;
+      o += M * (sys[i].n_nuc[0] + sys[i].n_nuc[1]) * 2;
+    }
+  }
+  // Systems small enough for the LDS-resident kernel run together in one launch per size class;
+  // the rest run tiled, grouped by term kernel (one job queue per group).
+  const int64_t zmax = sizeof(R) == 8 ? kResMax64 : kResMax32;
+  ResidentRun<R> res;
+  res.nB = nB;
+  res.M = M;
+  std::vector<TiledRun<R>> groups;
+  std::vector<int> group_kind;
+  for (int i = 0; i < n_sys; ++i) {
+    const rp_system *s = &sys[i];
+    SystemSpec spec = tile_order(make_spec(s->n_nuc[0], s->n_nuc[1], s->two_I, s->a_mT, s->J_mT, s->kS, s->kT,
+                                           s->T_us, gamma_of(s)));
+    const double *ang = angles ? angles + aoffs[i] : nullptr;
+    if (!(op.flags & RP_FLAG_TILED) && !log.on && !ps_t && spec.Z <= zmax) {
+      res.specs.push_back(spec);
+      res.B.push_back(B_mT + (int64_t)i * nB);
+      res.angles.push_back(ang);
+      res.out.push_back((int64_t)i * nB * M);
+      continue;
+    }
+    const int kind = term_kind_of(make_sysargs<R>(spec), op);
+    size_t g = 0;
+    while (g < groups.size() && group_kind[g] != kind) ++g;
+    if (g == groups.size()) {
+      groups.emplace_back();
+      groups.back().nB = nB;
+      groups.back().M = M;
+      groups.back().kind = kind;
+      group_kind.push_back(kind);
+    }
+    TiledSys ts;
+    ts.spec = spec;
+    ts.B = B_mT + (int64_t)i * nB;
+    ts.angles = ang;
+    ts.out = (int64_t)i * nB * M;
+    groups[g].sys.push_back(ts);
+  }
+  int rc;
+  int64_t need = 0;
+  if (!res.specs.empty()) {
+    if ((rc = res.prepare(op))) return rc;
+    need = res.bytes;
+  }
+  // Workspace budget: the caller's cap, else half of the free device memory; the static
+  // scratch area when there is one.
+  int64_t budget = scratch ? scratch_bytes : op.workspace;
+  if (budget <= 0) {
+    size_t fr = 0, tot = 0;
+    HIPCHK(hipMemGetInfo(&fr, &tot));
+    budget = (int64_t)(fr / 2);
+  }
+  const int64_t flag_bytes = 256;
+  if (scratch && need + flag_bytes > budget)   // (an allocated workspace takes the small resident tables beyond the cap)
+    return fail(RP_ENOMEM, "workspace of " + std::to_string(budget) + " bytes is too small for the LDS-resident jobs (" +
+                               std::to_string(need + flag_bytes) + " needed)");
+  for (auto &g : groups) {
+    if ((rc = g.prepare(op, budget - flag_bytes, op.workspace <= 0))) return rc;
+    need = std::max(need, g.fixed_bytes + g.chunk_bytes);
+  }
+  need += flag_bytes;
+  // One block for the call: stream-ordered, freed on the stream when the call ends.
+  struct Block {
+    void *p = nullptr;
+    hipStream_t s = nullptr;
+    bool async = false;
+    ~Block() {
+      if (!p) return;
+      if (async) (void)hipFreeAsync(p, s);
+      else (void)hipFree(p);
+    }
+  } blk;
+  char *base = scratch;
+  if (!scratch) {
+    blk.s = st;
+    if (hipMallocAsync(&blk.p, (size_t)need, st) == hipSuccess) {
+      blk.async = true;
+    } else {
+      (void)hipGetLastError();
+      if (hipMalloc(&blk.p, (size_t)need) != hipSuccess) {
+        (void)hipGetLastError();
+        blk.p = nullptr;
+        return fail(RP_ENOMEM, "device workspace of " + std::to_string(need) + " bytes could not be allocated");
+      }
+    }
+    base = (char *)blk.p;
+  }
+  int *flag = (int *)base;
+  hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(256), 0, st, (int32_t *)flag, 4, 0);
+  HIPCHK(hipGetLastError());
+  const bool use_graph = !log.on && !(op.flags & RP_FLAG_NO_GRAPH) && !scratch;
+  if (!res.specs.empty()) {
+    Arena ar{base + flag_bytes, need - flag_bytes, 0, false};
+    if ((rc = res.run(ar, op, phi, flag, st))) return rc;
+  }
+  for (auto &g : groups) {
+    Arena ar{base + flag_bytes, need - flag_bytes, 0, false};
+    if ((rc = g.run(ar, op, phi, ps_t, flag, use_graph, st, log))) return rc;
+  }
+  int h_flag = 0;
+  HIPCHK(hipMemcpyAsync(&h_flag, flag, sizeof(int), hipMemcpyDeviceToHost, st));
   HIPCHK(hipStreamSynchronize(st));
-  if (flag) return fail(RP_ENOTCONV, "wavepacket norm grew or became NaN (spectral bound violated)");
+  if (h_flag) return fail(RP_ENOTCONV, "wavepacket norm grew or became NaN (spectral bound violated)");
   return RP_OK;
 }
 
@@ -2439,7 +2830,8 @@ static int sia_system(const SystemSpec &spec, const double *B, int nB, const dou
         ia.stride[0] = 1;
         ia.d[0] = 1;
       }
-      hipLaunchKernelGGL(k_init<R>, dim3(grid), dim3(kBlock), 0, st, ia);
+      ia.tiles = (int64_t)grid;
+      hipLaunchKernelGGL((k_init<R, false>), dim3(grid), dim3(kBlock), 0, st, ia);
       HIPCHK(hipGetLastError());
     }
     std::vector<SiaJob> jobs(nj);
@@ -2556,46 +2948,10 @@ extern "C" int rp_propagate(const rp_system *sys, int32_t n_sys, const double *B
   log.on = (op.flags & RP_FLAG_PROFILE) != 0;
   if (log.on) g_prof = Profile();
   hipEvent_t t0 = log.mark(st);
-  // Systems small enough for the LDS-resident kernel run together in one launch per size class;
-  // the rest use the tiled kernels, one system at a time.
-  std::vector<int64_t> aoffs(n_sys, 0);
-  std::vector<int> resident;
-  {
-    int64_t o = 0;
-    const int64_t zmax = op.precision == 64 ? kResMax64 : kResMax32;
-    for (int i = 0; i < n_sys; ++i) {
-      aoffs[i] = o;
-      const int N = sys[i].n_nuc[0] + sys[i].n_nuc[1];
-      o += M * N * 2;
-      int64_t Z = 1;
-      for (int k = 0; k < N; ++k) Z *= sys[i].two_I[k] + 1;
-      if (!(op.flags & RP_FLAG_TILED) && !log.on && !ps_t && Z <= zmax) resident.push_back(i);
-    }
-  }
-  if (!resident.empty()) {
-    rc = op.precision == 64 ? propagate_resident<double>(resident, sys, B_mT, nB, angles, aoffs, M, op, phi, st)
-                            : propagate_resident<float>(resident, sys, B_mT, nB, angles, aoffs, M, op, phi, st);
-    if (rc) return rc;
-  }
-  int64_t aoff = 0;
-  for (int i = 0; i < n_sys; ++i) {
-    const rp_system *s = &sys[i];
-    const int N = s->n_nuc[0] + s->n_nuc[1];
-    if (std::find(resident.begin(), resident.end(), i) != resident.end()) {
-      aoff += M * N * 2;
-      continue;
-    }
-    SystemSpec spec = tile_order(make_spec(s->n_nuc[0], s->n_nuc[1], s->two_I, s->a_mT, s->J_mT, s->kS, s->kT,
-                                           s->T_us, gamma_of(s)));
-    const double *ang = angles ? angles + aoff : nullptr;
-    double *out = phi + (int64_t)i * nB * M;
-    double *pso = ps_t ? ps_t + (int64_t)i * nB * M * op.ps_len : nullptr;
-    rc = op.precision == 64
-             ? propagate_system<double>(spec, B_mT + (int64_t)i * nB, nB, ang, M, op, out, pso, st, log)
-             : propagate_system<float>(spec, B_mT + (int64_t)i * nB, nB, ang, M, op, out, pso, st, log);
-    if (rc) return rc;
-    aoff += M * N * 2;
-  }
+  rc = op.precision == 64
+           ? propagate_chebyshev<double>(sys, n_sys, B_mT, nB, angles, M, op, phi, ps_t, st, log, nullptr, 0)
+           : propagate_chebyshev<float>(sys, n_sys, B_mT, nB, angles, M, op, phi, ps_t, st, log, nullptr, 0);
+  if (rc) return rc;
   if (log.on) {
     hipEvent_t t1 = nullptr;
     if (hipEventCreate(&t1) == hipSuccess) {
