@@ -21,43 +21,66 @@ sys.path.insert(0, ROOT)
 PEAK_HBM_GBS = 8000.0
 
 
-def cpu_baseline(w, seconds_target=20.0):
-    """The CPU oracle (sparse augmented system, scipy expm_multiply) on a bounded sample:
-    one (sample, field) wavepacket at the sweep's middle field, over a fraction of the
-    horizon; cost is linear in the horizon, so the rate is scaled to full propagations."""
+def _oracle_worker(task):
+    """One oracle propagation (sparse augmented system) of the sweep workload over part of the
+    horizon: (sample index, field, horizon fraction) -> (fraction, seconds)."""
+    i, B, frac = task
     from oracle import large, philox
+    from paper_1612_09517_amd import workloads
+    w = workloads.sweep_c2()
     s = w.systems[0]
     sp = large.SparseSystem((s.n1, s.n2), s.two_I, s.a_mT, J_mT=s.J_mT, kS=s.kS, kT=s.kT, gamma=s.gamma)
-    B = float(np.median(w.fields_mT[0]))
-    a = philox.sample_angles(w.seed, 10 ** 6, 1, s.N)[0]
-    psi = sp.wavepacket(a)
-    frac = 0.05
+    a = philox.sample_angles(w.seed, 10 ** 6 + i, 1, s.N)[0]
     t0 = time.perf_counter()
-    large.yield_augmented(sp, B, s.T_us * frac, psi, tau=1.0)
-    dt = time.perf_counter() - t0
-    if dt < seconds_target / 2:   # a probe shorter than 10 s: time a longer stretch of the horizon
-        frac = min(1.0, frac * 0.75 * seconds_target / max(dt, 1e-3))
-        t0 = time.perf_counter()
-        large.yield_augmented(sp, B, s.T_us * frac, psi, tau=1.0)
-        dt = time.perf_counter() - t0
-    rate = frac / dt
-    # The oracle's hot loop is scipy's CSR sparse matrix-vector product, which runs on one core.
-    return {"value": rate, "unit": "propagations/s", "cores": 1, "kind": "oracle",
-            "sample": f"one wavepacket at B={B:.3f} mT over {frac * s.T_us:.3g} of {s.T_us} us "
-                      f"({dt:.1f} s), scaled linearly to the full horizon; host has {os.cpu_count()} cores"}
+    large.yield_augmented(sp, B, s.T_us * frac, sp.wavepacket(a), tau=1.0)
+    return frac, time.perf_counter() - t0
+
+
+def cpu_baseline(w, seconds_target=20.0):
+    """The CPU oracle (sparse augmented system, scipy expm_multiply) on every host core the box
+    gives this GPU: one process per core, each propagating its own wavepacket of the bench
+    workload at the sweep's middle field over the same part of the horizon (cost is linear in
+    the horizon, so the rate is stated in full propagations).  A one-process probe sizes the
+    part so that the parallel run takes about seconds_target."""
+    from multiprocessing import get_context
+    s = w.systems[0]
+    B = float(np.median(w.fields_mT[0]))
+    cores = max(1, min(16, os.cpu_count() or 1))
+    probe_frac = 0.01
+    _, dt = _oracle_worker((0, B, probe_frac))
+    frac = min(1.0, probe_frac * seconds_target / max(dt, 1e-3) * 0.8)
+    env = dict(OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1", MKL_NUM_THREADS="1")
+    old = {k: os.environ.get(k) for k in env}
+    os.environ.update(env)
+    try:
+        with get_context("spawn").Pool(cores) as pool:
+            t0 = time.perf_counter()
+            res = pool.map(_oracle_worker, [(i + 1, B, frac) for i in range(cores)], chunksize=1)
+            wall = time.perf_counter() - t0
+    finally:
+        for k, v in old.items():
+            if v is None:
+                os.environ.pop(k, None)
+            else:
+                os.environ[k] = v
+    rate = sum(f for f, _ in res) / wall
+    return {"value": rate, "unit": "propagations/s", "cores": cores, "kind": "oracle",
+            "sample": f"{cores} wavepackets in {cores} processes (one per core), B={B:.3f} mT, each over "
+                      f"{frac * s.T_us:.3g} of {s.T_us} us, {wall:.1f} s wall; rate in full propagations "
+                      f"(cost linear in the horizon); host has {os.cpu_count()} cores"}
 
 
 def term_kernel_digest():
     """SHA-256 of the source that decides the term kernel's memory traffic: the device
-    structures (kernels.hpp), the Chebyshev-term kernels of rp.hip and the host function that
-    sizes chunks and launches them (propagate_system)."""
+    structures (kernels.hpp), the Chebyshev-term kernels of rp.hip and the host code that
+    sizes chunks and launches them (TiledRun)."""
     import hashlib
     csrc = os.path.join(ROOT, "paper_1612_09517_amd", "csrc")
     hip = open(os.path.join(csrc, "rp.hip")).read()
     a = hip.index("// " + "-" * 77 + " Chebyshev term")
     b = hip.index("// " + "-" * 77 + " in-step quadrature")
-    c = hip.index("static int propagate_system(")
-    d = hip.index("\n}\n", c) + 3
+    c = hip.index("struct TiledRun {")
+    d = hip.index("\n};\n", c) + 4
     text = open(os.path.join(csrc, "kernels.hpp")).read() + hip[a:b] + hip[c:d]
     return hashlib.sha256(text.encode()).hexdigest()
 
@@ -177,6 +200,160 @@ def cv_headline(args):
            "cv_minus_plain_over_err": float(np.max(np.abs(m_cv - m_pl) / np.sqrt(e_cv ** 2 + e_pl ** 2))),
            "combined_minus_plain_over_err": float(np.max(np.abs(m_cb - m_pl) / np.sqrt(e_cb ** 2 + e_pl ** 2)))}
     print(json.dumps(rec), flush=True)
+
+
+def sequential_sweep(nB, eps, initial, draw, stats, say, label):
+    """The stopping rule every estimator of the headline shares: each round draws fresh units
+    (samples, or design groups) for the fields whose standard error is still above eps, as many
+    as n (err / eps_f)^2 x 1.05 from the current error (at least one more), until none is.
+    draw(fields, n, first) -> CUDA [len(fields)][n] new units; stats(f, units) -> (mean, err,
+    ratio): the estimate, its error, and the ratio of the units' own error to the error they
+    must reach (err / eps, or a smaller target when another estimate is combined in).  Returns
+    per-field means, errors, unit counts and rounds."""
+    import torch
+    store = [None] * nB
+    done = np.zeros(nB, int)
+    need = np.full(nB, initial)
+    mean, err = np.zeros(nB), np.full(nB, np.inf)
+    rounds = 0
+    while True:
+        todo = np.nonzero(need > done)[0]
+        if todo.size == 0:
+            break
+        n = int(np.max(need[todo] - done[todo]))
+        first = int(done[todo].max())
+        new = draw(todo, n, first)
+        for j, f in enumerate(todo):
+            store[f] = new[j] if store[f] is None else torch.cat([store[f], new[j]])
+            done[f] = store[f].numel()
+            m, e, ratio = stats(f, store[f])
+            mean[f], err[f] = m, e
+            need[f] = done[f] if e <= eps else max(done[f] + 1, int(np.ceil(done[f] * ratio ** 2 * 1.05)))
+        rounds += 1
+        say(f"{label}: round {rounds}, {int(done.sum())} units, max error {err.max():.2e}")
+    return mean, err, done, rounds
+
+
+def headline_sweeps(args, say):
+    """Measured sweeps to eps <= 1e-3 at every field of the control-variate workload (the first
+    N=14 system of the batched set: Z = 2^14, 32 fields 0..5 mT, T = 20 us): plain Monte Carlo
+    with complex-FP64 wavepackets (the baseline), complex FP32 with the strength-2 sign-flip
+    design (groups of 16), and complex FP32 with the learned control variate (training-yield
+    generation, training and the mean of the network included) combined with the training
+    yields' own plain mean.  Each leg is timed end to end on the GPU with the same sequential
+    stopping rule; samples come from separate seeds."""
+    import torch
+    from paper_1612_09517_amd import cv, rp, workloads
+    w = workloads.cv_c5()
+    s = w.systems[0]
+    B = w.fields_mT[0]
+    nB = len(B)
+    eps = 1e-3
+    sync = torch.cuda.synchronize
+    legs = set(args.headline_legs.split(","))
+    out = {"workload": f"{w.systems[0].name}: N=14 spin-1/2 (7+7), Z=16384, {nB} fields {B[0]:g}..{B[-1]:g} mT, "
+                       f"T={s.T_us:g} us, kS={s.kS:.4f}, kT={s.kT:.4f} /us",
+           "eps": eps, "rule": "rounds of fresh units for the fields whose standard error is above eps, "
+                               "n (err/eps)^2 x 1.05 each, until every field is at or below eps"}
+
+    def propagate_fields(fields, ang, n, prec):
+        parts = []
+        for c0 in range(0, len(fields), 16):
+            fs = fields[c0:c0 + 16]
+            parts.append(rp.propagate(s, B[fs][None, :], ang, n, precision=prec)[0])
+        return torch.cat(parts)
+
+    def plain_stats(f, u):
+        m, e = rp.yield_stats(u[None, :])
+        return float(m[0]), float(e[0]), float(e[0]) / eps
+
+    means = {}
+    if "fp64" in legs:
+        sync()
+        t0 = time.perf_counter()
+        props = [0]
+
+        def draw64(fields, n, first):
+            props[0] += n * len(fields)
+            return propagate_fields(fields, rp.sample(s, w.seed + 1, n, first=first), n, 64)
+
+        m, e, done, rounds = sequential_sweep(nB, eps, 64, draw64, plain_stats, say, "plain FP64")
+        sync()
+        wall = time.perf_counter() - t0
+        means["plain_fp64"] = (m, e)
+        out["plain_fp64"] = {"wall_s": wall, "propagations": props[0], "rate_props_s": props[0] / wall,
+                             "samples_per_field_max": int(done.max()), "rounds": rounds, "err_max": float(e.max())}
+    if "design" in legs:
+        mode = 5
+        R = rp.design_size(s.N, mode)
+        sync()
+        t0 = time.perf_counter()
+        props = [0]
+
+        def draw_design(fields, G, first):
+            props[0] += G * R * len(fields)
+            ang = rp.sample(s, w.seed + 2, G * R, first=first * R, basis_mode=mode)
+            return rp.group_mean(propagate_fields(fields, ang, G * R, 32), R)
+
+        m, e, done, rounds = sequential_sweep(nB, eps, 8, draw_design, plain_stats, say, "FP32 design")
+        sync()
+        wall = time.perf_counter() - t0
+        means["design_fp32"] = (m, e)
+        out["design_fp32"] = {"wall_s": wall, "propagations": props[0], "rate_props_s": props[0] / wall,
+                              "design": f"rp_sample mode {mode}, {R} samples per group (orthogonal array of strength 2)",
+                              "groups_per_field_max": int(done.max()), "rounds": rounds, "err_max": float(e.max())}
+    if "cv" in legs:
+        sync()
+        t0 = time.perf_counter()
+        c = cv.ControlVariate(s, B, seed=w.seed, width=256, depth=3, precision=32)
+        a_tr, phi_tr = c.generate_training(args.cv_train // nB)
+        sync()
+        t_gen = time.perf_counter() - t0
+        say(f"control variate: {args.cv_train // nB * nB} training yields in {t_gen:.1f} s")
+        val = c.train(a_tr, phi_tr, epochs=args.cv_epochs, batch=512, lr=1e-3, augment=True)
+        sync()
+        t_fit = time.perf_counter() - t0 - t_gen
+        c.fit_mu(args.cv_quad)
+        tr_m, tr_e = c.train_mean.cpu().numpy(), c.train_err.cpu().numpy()
+        say(f"control variate: trained (validation mse {val:.3f}), mu fitted")
+        props = [args.cv_train // nB * nB]
+        gs = [None] * nB
+
+        def draw_cv(fields, n, first):
+            props[0] += n * len(fields)
+            ang = rp.sample(s, w.seed, n, first=first, stream_id=cv.STREAM_EVAL)
+            phi = propagate_fields(fields, ang, n, 32)
+            g = c.g(ang)[fields]
+            for j, f in enumerate(fields):
+                gs[f] = g[j] if gs[f] is None else torch.cat([gs[f], g[j]])
+            return phi
+
+        def cv_stats(f, u):
+            m, e = rp.yield_stats(u[None, :], gs[f][None, :], c.mu[f:f + 1], c.beta[f:f + 1], c.mu_err[f:f + 1])
+            mc, ec = rp.combine(m, e, c.train_mean[f:f + 1], c.train_err[f:f + 1])
+            # combined with the training mean, the control-variate estimate itself must reach
+            # (1/eps^2 - 1/err_train^2)^(-1/2)
+            tgt = np.inf if tr_e[f] <= eps else (1.0 / eps ** 2 - 1.0 / tr_e[f] ** 2) ** -0.5
+            return float(mc[0]), float(ec[0]), float(e[0]) / tgt
+
+        m, e, done, rounds = sequential_sweep(nB, eps, 16, draw_cv, cv_stats, say, "FP32 control variate")
+        sync()
+        wall = time.perf_counter() - t0
+        means["cv_fp32"] = (m, e)
+        out["cv_fp32"] = {"wall_s": wall, "propagations": props[0],
+                          "train": {"yields": args.cv_train // nB * nB, "generate_s": t_gen, "fit_s": t_fit,
+                                    "epochs_run": len(c.history), "val_mse_standardised": val,
+                                    "mu_samples": args.cv_quad, "net": "3x256 GELU, BF16 MFMA, FP32 master weights"},
+                          "eval_samples_per_field_max": int(done.max()), "rounds": rounds,
+                          "err_max": float(e.max())}
+    if "plain_fp64" in means:
+        m64, e64 = means["plain_fp64"]
+        for k in ("design_fp32", "cv_fp32"):
+            if k in means:
+                m, e = means[k]
+                out[k]["speedup_vs_plain_fp64"] = out["plain_fp64"]["wall_s"] / out[k]["wall_s"]
+                out[k]["max_dev_from_plain_fp64_over_err"] = float(np.max(np.abs(m - m64) / np.sqrt(e ** 2 + e64 ** 2)))
+    return out
 
 
 def other_workload(args):
@@ -498,9 +675,15 @@ def histogram(args):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=2)
-    ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--samples-per-step", type=int, default=8)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--samples-per-step", type=int, default=2)
+    ap.add_argument("--profile-steps", type=int, default=2,
+                    help="extra steps with HIP events around the term launches (roofline)")
+    ap.add_argument("--no-headline", action="store_true",
+                    help="skip the measured sweeps to eps <= 1e-3 (plain FP64, FP32 + design, FP32 + control variate)")
+    ap.add_argument("--headline-legs", default="fp64,design,cv",
+                    help="which measured sweeps to run (comma-separated subset of fp64,design,cv)")
     ap.add_argument("--fields", type=int, default=64)
     ap.add_argument("--precision", type=int, default=32, choices=[32, 64])
     ap.add_argument("--rdt", type=float, default=0.0)
@@ -509,8 +692,6 @@ def main():
     ap.add_argument("--workspace-gb", type=float, default=0.0,
                     help="device workspace cap per call (bounds how many wavepackets run together)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-fp64-probe", action="store_true",
-                    help="skip the untimed plain-FP64 rate probe of the default bench line")
     ap.add_argument("--copy-probe", type=float, default=0.0,
                     help="only copy a buffer of this many GiB three times (calibrates HBM counters)")
     ap.add_argument("--workload", default="sweep",
@@ -595,7 +776,11 @@ def main():
     B = w.fields_mT
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
-    stream = torch.cuda.current_stream()
+    t_start = time.perf_counter()
+
+    def say(msg):
+        print(json.dumps({"progress": msg, "t_s": round(time.perf_counter() - t_start, 1)}), file=sys.stderr,
+              flush=True)
 
     tuned = {"rdt": args.rdt, "xcd": None}
     if args.autotune:
@@ -609,41 +794,28 @@ def main():
         mean, err = rp.yield_stats(phi[0])
         return phi, mean, err
 
+    # Throughput: the production path (captured step graphs, no events), K timed steps.
     for i in range(args.warmup):
         step(1000 + i)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    prof = {"term_ms": 0.0, "term_launches": 0.0, "elements": 0.0, "quad_ms": 0.0, "total_ms": 0.0}
-    phis = []
     for i in range(args.steps):
-        phi, mean, err = step(i, profile=True)
+        step(i)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    props = args.steps * Mb * B.shape[1]
+    value = props / elapsed
+    say(f"throughput: {value:.1f} propagations/s")
+    # Roofline: one more step with HIP events around the term launches (on the call's stream).
+    prof = {"term_ms": 0.0, "term_launches": 0.0, "elements": 0.0, "quad_ms": 0.0, "total_ms": 0.0}
+    for i in range(args.profile_steps):
+        step(args.steps + i, profile=True)
         p = rp.profile_last()
         for k in prof:
             prof[k] += p[k]
         bpe = p["bytes_per_element"]
         nterms = p["terms_per_step"]
-        phis.append(phi[0].cpu().numpy())
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    props = args.steps * Mb * B.shape[1]
-    value = props / elapsed
-    phi_all = np.concatenate(phis, axis=1)
-    sig = phi_all.std(axis=1, ddof=1)
-    M_needed = np.ceil((sig / 1e-3) ** 2)
-    sweep_props = float(M_needed.max()) * B.shape[1]
     achieved = prof["elements"] * bpe / (prof["term_ms"] * 1e-3) / 1e9
-    plain64 = None
-    if args.precision == 32 and not args.no_fp64_probe:
-        # untimed: the plain FP64 rate on the same fields, for the sweep wall time it implies
-        M64 = 2
-        ang64 = rp.sample(s, w.seed, M64, first=10 ** 6)
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        rp.propagate(s, B, ang64, M64, precision=64)
-        torch.cuda.synchronize()
-        rate64 = M64 * B.shape[1] / (time.perf_counter() - t1)
-        plain64 = {"propagations_per_s": rate64, "sweep_wall_s_at_eps_1e-3": sweep_props / rate64,
-                   "sample": f"{M64} samples x {B.shape[1]} fields, complex FP64, one call"}
     rec = {
         "metric": "sweep wall time at sigma(Phi_S)<=1e-3 vs plain FP64 MC; H.psi HBM GB/s vs peak",
         "value": value,
@@ -661,9 +833,8 @@ def main():
                                f"{B.shape[1]} fields 0..10 mT x {Mb} samples per step",
                    "Z": s.Z, "dim": s.dim, "fields": int(B.shape[1]), "samples_per_step": Mb,
                    "precision": f"complex-FP{args.precision} state, FP64 coefficients and reductions",
-                   "launch": {"rdt": tuned["rdt"] or 100.0,
-                              "xcd": tuned["xcd"] or "default",
-                              "autotuned": bool(args.autotune)}},
+                   "launch": {"rdt": tuned["rdt"] or 100.0, "xcd": tuned["xcd"] or "default",
+                              "autotuned": bool(args.autotune), "graphs": True}},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": achieved / PEAK_HBM_GBS,
                      "traffic": measured_traffic(args.precision, int(nterms),
@@ -673,13 +844,14 @@ def main():
                                 "k_cheb_tile (Chebyshev term") + "; three launch variants)",
                      "avg_launch_us": prof["term_ms"] * 1e3 / max(prof["term_launches"], 1),
                      "bytes_per_element_term": bpe, "terms_per_step": nterms,
+                     "profiled_steps": args.profile_steps,
                      "term_time_frac": prof["term_ms"] / max(prof["total_ms"], 1e-9),
                      "quad_time_frac": prof["quad_ms"] / max(prof["total_ms"], 1e-9)},
-        "sigma_max": float(sig.max()),
-        "sweep_wall_s_at_eps_1e-3": sweep_props / value,
-        "plain_fp64": plain64,
     }
+    if not args.no_headline:
+        rec["sweep_to_eps"] = headline_sweeps(args, say)
     if not args.no_cpu_baseline:
+        say("cpu baseline")
         rec["cpu_baseline"] = cpu_baseline(w)
     print(json.dumps(rec), flush=True)
 

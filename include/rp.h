@@ -73,7 +73,8 @@ typedef struct rp_opts {
   double rdt;               /* target r*dt of one Chebyshev step (r = spectral half-width); 0 = 100 */
   double r_scale;           /* multiplies the spectral half-width bound; 0 selects 1.  Values below 1
                                under-estimate the spectrum and exist to test RP_ENOTCONV. */
-  int64_t workspace_bytes;  /* cap on device workspace per call; 0 selects half of free memory */
+  int64_t workspace_bytes;  /* cap on the device memory of the wavepacket chunks of a call (the call's
+                               coefficient tables come on top); 0 selects half of free memory */
   int32_t flags;            /* bit mask of RP_FLAG_* */
   int32_t krylov_dim;       /* Krylov dimension m of the short-iterative Arnoldi propagator
                                (RP_FLAG_ARNOLDI); 0 selects 16, otherwise 2..32 */
@@ -188,10 +189,16 @@ int64_t rp_design_size(int32_t n_nuclei, int32_t basis_mode);
  * of Bessel functions, factored by pivoted Cholesky).  With RP_FLAG_ARNOLDI the
  * short-iterative Arnoldi propagator is used instead (see that flag).
  *
- * Workspace: the call allocates device memory for its chunk of wavepackets (three
- * vectors of 4Z complex numbers per job plus the singlet amplitudes of one step,
- * N_terms x Z per job), at most opts->workspace_bytes or half of the free memory,
- * and frees it before returning.
+ * Several systems in one call: systems with at most 1024 (complex FP32) or 512 (FP64)
+ * nuclear states run in the LDS-resident kernel; the others share one job queue per term
+ * kernel, so that wavepackets of unequal Z are propagated by the same launches.
+ *
+ * Workspace: one block of device memory per call, taken on hip_stream with hipMallocAsync
+ * and returned with hipFreeAsync (stream-ordered; hipMalloc / hipFree where that is not
+ * available): the call's tables plus the largest chunk of wavepackets (three vectors of 4Z
+ * complex numbers per job plus the singlet amplitudes of one step, N_terms x Z per job),
+ * with chunks cut so that the chunk buffers stay within opts->workspace_bytes, else the
+ * whole block within half of the free memory.
  */
 int rp_propagate(const rp_system *sys, int32_t n_sys, const double *B_mT, int32_t nB,
                  const double *angles, int64_t M, const rp_opts *opts, double *phi, double *ps_t,

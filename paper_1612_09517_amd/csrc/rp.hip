@@ -1567,7 +1567,8 @@ struct TiledRun {
     return z.used;
   }
 
-  int prepare(const Opts &op, int64_t budget, bool default_chunks) {
+  // budget: bytes for the chunk buffers, and for the tables too when tables_in_budget.
+  int prepare(const Opts &op, int64_t budget, bool tables_in_budget, bool default_chunks) {
     const int ns = (int)sys.size();
     std::vector<const SystemSpec *> specs;
     std::vector<const double *> Bs;
@@ -1645,7 +1646,7 @@ struct TiledRun {
     f.add<double>(2 * ns);
     f.add<cx<double>>(tab_rows * (RP_MAX_TWO_I + 1));
     fixed_bytes = f.used;
-    const int64_t region = budget - fixed_bytes;
+    const int64_t region = tables_in_budget ? budget - fixed_bytes : budget;
     // Chunks: consecutive jobs while the workspace allows; by default the chunk's three
     // wavepacket buffers stay within 192 MB (resident in the 256 MB Infinity Cache across
     // launches) unless that leaves fewer than 64 jobs; fewer than 2^24 workgroups per launch.
@@ -2244,7 +2245,10 @@ static int propagate_chebyshev(const rp_system *sys, int n_sys, const double *B_
     return fail(RP_ENOMEM, "workspace of " + std::to_string(budget) + " bytes is too small for the LDS-resident jobs (" +
                                std::to_string(need + flag_bytes) + " needed)");
   for (auto &g : groups) {
-    if ((rc = g.prepare(op, budget - flag_bytes, op.workspace <= 0))) return rc;
+    // An explicit cap (opts->workspace_bytes) bounds the chunk buffers; the call's tables come
+    // on top.  The static area and the default budget hold everything.
+    const bool capped = !scratch && op.workspace > 0;
+    if ((rc = g.prepare(op, capped ? budget : budget - flag_bytes, !capped, op.workspace <= 0))) return rc;
     need = std::max(need, g.fixed_bytes + g.chunk_bytes);
   }
   need += flag_bytes;
@@ -2893,15 +2897,18 @@ static int sia_system(const SystemSpec &spec, const double *B, int nB, const dou
   return RP_OK;
 }
 
-extern "C" int rp_propagate(const rp_system *sys, int32_t n_sys, const double *B_mT, int32_t nB,
-                            const double *angles, int64_t M, const rp_opts *opts, double *phi, double *ps_t,
-                            void *hip_stream) {
-  g_err.clear();
+// Argument checks shared by rp_propagate and rp_propagate_static (RP_OK, or an error code; *empty
+// is set when there is nothing to do).
+static int check_propagate(const rp_system *sys, int32_t n_sys, const double *B_mT, int32_t nB, const double *angles,
+                           int64_t M, const rp_opts *opts, double *phi, double *ps_t, Opts &op, bool &empty) {
+  empty = false;
   if (n_sys < 0 || nB < 0 || M < 0) return fail(RP_EINVAL, "negative count");
-  if (n_sys == 0 || nB == 0 || M == 0) return RP_OK;
+  if (n_sys == 0 || nB == 0 || M == 0) {
+    empty = true;
+    return RP_OK;
+  }
   if (!sys || !B_mT || !phi) return fail(RP_EINVAL, "null pointer");
   if (M > (int64_t)1 << 31) return fail(RP_EINVAL, "M too large");
-  Opts op;
   int rc = read_opts(opts, op);
   if (rc) return rc;
   if (ps_t && (op.flags & RP_FLAG_ARNOLDI))
@@ -2915,6 +2922,17 @@ extern "C" int rp_propagate(const rp_system *sys, int32_t n_sys, const double *B
   }
   for (int64_t i = 0; i < (int64_t)n_sys * nB; ++i)
     if (!std::isfinite(B_mT[i])) return fail(RP_EINVAL, "non-finite field");
+  return RP_OK;
+}
+
+extern "C" int rp_propagate(const rp_system *sys, int32_t n_sys, const double *B_mT, int32_t nB,
+                            const double *angles, int64_t M, const rp_opts *opts, double *phi, double *ps_t,
+                            void *hip_stream) {
+  g_err.clear();
+  Opts op;
+  bool empty = false;
+  int rc = check_propagate(sys, n_sys, B_mT, nB, angles, M, opts, phi, ps_t, op, empty);
+  if (rc || empty) return rc;
   hipStream_t st = (hipStream_t)hip_stream;
   // The legacy default stream cannot be captured into a graph: run the call on a blocking
   // stream of its own (implicitly ordered with the default stream; the call synchronises

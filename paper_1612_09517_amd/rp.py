@@ -186,9 +186,9 @@ def propagate(systems, B_mT, angles, M, precision=64, init_mode=0, tol=0.0, rdt=
         flags |= RP_FLAG_XCD_SPREAD
     o = _opts(precision, init_mode, tol, rdt, r_scale, workspace_bytes, flags, max_growth, krylov_dim, ps_t_len)
     ps = torch.empty((len(systems), nB, M, ps_t_len), dtype=torch.float64, device="cuda") if ps_t_len > 0 else None
-    _check(lib().rp_propagate(arr, len(cs), B.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), nB, ang, M,
-                              ctypes.byref(o), _dev_ptr(out, torch.float64), _dev_ptr(ps, torch.float64),
-                              _stream(torch)))
+    fn = lib().rp_propagate
+    _check(fn(arr, len(cs), B.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), nB, ang, M, ctypes.byref(o),
+              _dev_ptr(out, torch.float64), _dev_ptr(ps, torch.float64), _stream(torch)))
     return (out, ps) if ps is not None else out
 
 

@@ -283,6 +283,35 @@ def test_multi_system_call_and_chunking_are_consistent():
     assert np.array_equal(again, two)
 
 
+def test_job_queue_of_unequal_tiled_systems():
+    """Tiled systems of unequal Z in one call share the Chebyshev launches (job queue: per-tile
+    job index, per-job offsets, per-system constants): the yields agree with one call per
+    system (uniform launches) to the rounding of a possibly different FMA contraction, with the
+    oracle for the smallest, and with a workspace small enough to cut the queue into chunks
+    that mix systems differently."""
+    rng = np.random.default_rng(31)
+    systems = [SpinSystem(6, 5, [1] * 11, list(rng.normal(0, 0.7, 11)), kS=1.6, kT=2.9, T_us=0.4),
+               SpinSystem(4, 4, [1] * 8, list(rng.normal(0, 0.7, 8)), kS=0.3, kT=0.2, T_us=0.9),
+               SpinSystem(7, 6, [1] * 13, list(rng.normal(0, 0.7, 13)), J_mT=0.1, kS=0.5, kT=0.8, T_us=0.3),
+               SpinSystem(5, 5, [1] * 10, list(rng.normal(0, 0.7, 10)), kS=2.0, kT=0.5, T_us=0.6)]
+    B = np.array([[0.0, 2.0, 5.0]] * len(systems))
+    M = 4
+    angs = [rp.sample(s, 20 + i, M) for i, s in enumerate(systems)]
+    cat = torch.cat([a.reshape(-1) for a in angs])
+    for prec, tol in ((64, 1e-12), (32, 2e-6)):
+        _say("job queue, precision", prec, "Z =", [s.Z for s in systems])
+        both = rp.propagate(systems, B, cat, M, precision=prec, tiled=True).cpu().numpy()
+        one = np.stack([rp.propagate(s, B[i:i + 1], angs[i], M, precision=prec, tiled=True).cpu().numpy()[0]
+                        for i, s in enumerate(systems)])
+        _say("  queue against one call per system:", _rel(both, one), "bit-identical:", np.array_equal(both, one))
+        assert _rel(both, one) < tol
+        ws = 3 * (12 + 160) * max(s.Z for s in systems) * (16 if prec == 64 else 8)   # about three of the largest
+        small = rp.propagate(systems, B, cat, M, precision=prec, tiled=True, workspace_bytes=ws).cpu().numpy()
+        assert _rel(small, both) < tol
+        want = gc.oracle_phi_sparse(systems[1], B[1], philox.sample_angles(21, 0, M, systems[1].N))
+        assert _rel(both[1], want) < TOL[prec]
+
+
 # --------------------------------------------------------------------------- statistics and errors
 def test_yield_statistics():
     rng = np.random.default_rng(2)
