@@ -205,6 +205,30 @@ int rp_propagate(const rp_system *sys, int32_t n_sys, const double *B_mT, int32_
                  void *hip_stream);
 
 /*
+ * rp_propagate_static -- rp_propagate without any device allocation, for callers that cannot
+ * allocate device memory (code near graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  Same arguments, outputs and errors as rp_propagate; the caller still passes the
+ * inputs and outputs.
+ *
+ * Workspace: a static device area of RP_STATIC_SCRATCH_MB MiB that the library holds on every
+ * GPU it runs on (its own copy per GPU) until the process ends, instead of a per-call
+ * allocation.  Calls whose tables plus one wavepacket's buffers (three vectors of 4Z complex
+ * numbers and N_terms x Z singlet amplitudes) exceed it return RP_ENOMEM with the sizes in
+ * rp_last_error(); larger calls are cut into chunks that fit.  opts->workspace_bytes must be
+ * 0; RP_FLAG_ARNOLDI and RP_FLAG_PROFILE return RP_ENOTIMPL.  Kernels are launched directly
+ * (no internal graph capture; every buffer clear is a kernel, not a memset), and the call
+ * waits for its work before returning, as rp_propagate does.
+ *
+ * Every call on a GPU shares that GPU's area and leaves its last contents there: calls that
+ * overlap on one GPU (several host threads, or several streams without ordering between the
+ * calls) race and must be serialised by the caller.
+ */
+#define RP_STATIC_SCRATCH_MB 256
+int rp_propagate_static(const rp_system *sys, int32_t n_sys, const double *B_mT, int32_t nB,
+                        const double *angles, int64_t M, const rp_opts *opts, double *phi, double *ps_t,
+                        void *hip_stream);
+
+/*
  * rp_yield -- per-field Monte Carlo mean and standard error (Eq. 18, Eq. 23:
  * eps = s / sqrt(M), s with the 1/(M-1) normalisation).
  *

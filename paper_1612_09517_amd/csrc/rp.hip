@@ -19,6 +19,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <numeric>
 #include <string>
 #include <type_traits>
@@ -2987,6 +2988,54 @@ extern "C" int rp_propagate(const rp_system *sys, int32_t n_sys, const double *B
     log.resolve(g_prof);
   }
   return RP_OK;
+}
+
+// ----------------------------------------------------------------------------- without allocation
+// The workspace of rp_propagate_static: a file-scope device array that every GPU the library
+// runs on holds (its own copy, at its own address) until the process ends.  In host code the
+// name `scratch` is only a host-side stand-in: kernels and copies get the device address that
+// hipGetSymbolAddress reports for the current device, looked up once per device.
+constexpr int64_t kScratchBytes = (int64_t)RP_STATIC_SCRATCH_MB << 20;
+static __device__ __align__(256) char scratch[kScratchBytes];
+
+static std::mutex g_scratch_mu;
+static char *g_scratch_ptr[64];   // device address of `scratch` per device id (null until looked up)
+
+static int scratch_address(char **out) {
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= 64) return fail(RP_EDEVICE, "device id out of range for the static scratch table");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return fail(RP_EDEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    g_scratch_ptr[dev] = (char *)p;
+  }
+  *out = g_scratch_ptr[dev];
+  return RP_OK;
+}
+
+extern "C" int rp_propagate_static(const rp_system *sys, int32_t n_sys, const double *B_mT, int32_t nB,
+                                   const double *angles, int64_t M, const rp_opts *opts, double *phi, double *ps_t,
+                                   void *hip_stream) {
+  g_err.clear();
+  Opts op;
+  bool empty = false;
+  int rc = check_propagate(sys, n_sys, B_mT, nB, angles, M, opts, phi, ps_t, op, empty);
+  if (rc || empty) return rc;
+  if (op.flags & (RP_FLAG_ARNOLDI | RP_FLAG_PROFILE))
+    return fail(RP_ENOTIMPL, "rp_propagate_static: RP_FLAG_ARNOLDI and RP_FLAG_PROFILE need rp_propagate");
+  if (op.workspace > 0 && op.workspace < kScratchBytes)
+    return fail(RP_EINVAL, "rp_propagate_static: workspace_bytes must be 0 (the static area is used whole)");
+  char *base = nullptr;
+  if ((rc = scratch_address(&base))) return rc;
+  EventLog log;   // off: no events
+  hipStream_t st = (hipStream_t)hip_stream;
+  return op.precision == 64
+             ? propagate_chebyshev<double>(sys, n_sys, B_mT, nB, angles, M, op, phi, ps_t, st, log, base, kScratchBytes)
+             : propagate_chebyshev<float>(sys, n_sys, B_mT, nB, angles, M, op, phi, ps_t, st, log, base, kScratchBytes);
 }
 
 extern "C" int rp_profile_last(double *out, int32_t n) {

@@ -41,7 +41,7 @@ _lib = None
 EXPORTS = ["rp_sample", "rp_propagate", "rp_yield", "rp_strerror", "rp_last_error", "rp_bessel_j",
            "rp_plan_field", "rp_profile_last", "rp_mlp_param_count", "rp_mlp_workspace_floats",
            "rp_mlp_features", "rp_mlp_forward", "rp_mlp_train_step", "rp_cv_beta", "rp_combine",
-           "rp_design_size", "rp_group_mean"]
+           "rp_design_size", "rp_group_mean", "rp_propagate_static"]
 RP_FLAG_PROFILE = 1
 RP_FLAG_TILED = 2
 RP_FLAG_XCD_LOCAL = 4
@@ -64,6 +64,7 @@ def lib():
         op = ctypes.POINTER(_Opts)
         L.rp_sample.argtypes = [sp, u64, u32, u64, i64, i32, vp, vp]
         L.rp_propagate.argtypes = [sp, i32, dp, i32, vp, i64, op, vp, vp, vp]
+        L.rp_propagate_static.argtypes = [sp, i32, dp, i32, vp, i64, op, vp, vp, vp]
         L.rp_yield.argtypes = [vp, i32, i64, vp, vp, vp, vp, vp, vp, vp]
         L.rp_mlp_param_count.argtypes = [i32, i32, i32]
         L.rp_mlp_param_count.restype = i64
@@ -84,7 +85,7 @@ def lib():
         L.rp_bessel_j.argtypes = [ctypes.c_double, i32, dp]
         L.rp_plan_field.argtypes = [sp, ctypes.c_double, op, dp, dp, dp]
         L.rp_profile_last.argtypes = [dp, i32]
-        for f in ("rp_sample", "rp_propagate", "rp_yield", "rp_bessel_j", "rp_plan_field", "rp_profile_last",
+        for f in ("rp_sample", "rp_propagate", "rp_propagate_static", "rp_yield", "rp_bessel_j", "rp_plan_field", "rp_profile_last",
                   "rp_mlp_features", "rp_mlp_forward", "rp_mlp_train_step", "rp_cv_beta", "rp_combine",
                   "rp_group_mean"):
             getattr(L, f).restype = ctypes.c_int
@@ -157,8 +158,10 @@ def sample(system: SpinSystem, seed, M, first=0, stream_id=0, basis_mode=0, out=
 
 def propagate(systems, B_mT, angles, M, precision=64, init_mode=0, tol=0.0, rdt=0.0, r_scale=0.0,
               workspace_bytes=0, out=None, profile=False, tiled=False, xcd=None, graph=True, max_growth=0.0,
-              arnoldi=False, krylov_dim=0, term_scalar=False, ps_t_len=0):
+              arnoldi=False, krylov_dim=0, term_scalar=False, ps_t_len=0, static=False):
     """rp_propagate: single-wavepacket yields [n_sys][nB][M] (float64 CUDA tensor).
+    With ``static`` the call goes to rp_propagate_static (no device allocation inside the
+    library: its static workspace area instead).
 
     ``systems`` is a SpinSystem or a list; ``B_mT`` is [n_sys][nB] (host);
     ``angles`` is the concatenation of the per-system [M][N][2] arrays (CUDA).
@@ -186,7 +189,7 @@ def propagate(systems, B_mT, angles, M, precision=64, init_mode=0, tol=0.0, rdt=
         flags |= RP_FLAG_XCD_SPREAD
     o = _opts(precision, init_mode, tol, rdt, r_scale, workspace_bytes, flags, max_growth, krylov_dim, ps_t_len)
     ps = torch.empty((len(systems), nB, M, ps_t_len), dtype=torch.float64, device="cuda") if ps_t_len > 0 else None
-    fn = lib().rp_propagate
+    fn = lib().rp_propagate_static if static else lib().rp_propagate
     _check(fn(arr, len(cs), B.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), nB, ang, M, ctypes.byref(o),
               _dev_ptr(out, torch.float64), _dev_ptr(ps, torch.float64), _stream(torch)))
     return (out, ps) if ps is not None else out
