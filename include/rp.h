@@ -115,6 +115,10 @@ typedef struct rp_opts {
    256-index tile kernel, 8-byte accesses) instead of two per thread with 16-byte accesses.
    Same sums in the same order; for comparison. */
 #define RP_FLAG_TERM_SCALAR 64
+/* opts->flags: internal nuclear axis order with the higher spins on the fastest axes (and the
+   mixed-radix term kernel) instead of the spin-1/2 nuclei first (the 256-index tile kernels).
+   Same yields up to rounding; a candidate of the autotuner for systems that mix spins. */
+#define RP_FLAG_AXES_HIGH_FIRST 128
 
 /*
  * rp_sample -- directions of the nuclear coherent states (Eq. 18: uniform on

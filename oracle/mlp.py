@@ -7,7 +7,10 @@ Parameters are packed per hidden layer as W [fan_in][width] then b [width], foll
 the output weights [width] and the output bias.  Optimiser: Adam (Kingma & Ba 2015).
 
 Parity status: the forward pass is the definition written out; the backward pass is
-pinned by central finite differences of the forward pass in the tests.
+pinned by central finite differences of the forward pass in the tests.  ``forward`` and
+``loss_and_grad`` take an optional operand map ``q`` applied to both operands of every
+hidden-layer product (the identity by default, so the oracle stays FP64); a test may pass a
+rounding of its own to model a device that rounds those operands.
 """
 import numpy as np
 from scipy.special import erf
@@ -89,20 +92,26 @@ def features(angles, B_mT, rot_seed=0):
     return x
 
 
-def forward(p, x, n_in, width, depth):
+def _identity(a):
+    return a
+
+
+def forward(p, x, n_in, width, depth, q=None):
+    q = q or _identity
     layers, w, bo = unpack(p, n_in, width, depth)
     h = np.asarray(x, float)
     cache = []
     for W, b in layers:
-        z = h @ W + b
+        z = q(h) @ q(W) + b
         cache.append((h, z))
         h = gelu(z)
     return h @ w + bo, (cache, h)
 
 
-def loss_and_grad(p, x, t, n_in, width, depth):
+def loss_and_grad(p, x, t, n_in, width, depth, q=None):
+    q = q or _identity
     layers, w, bo = unpack(p, n_in, width, depth)
-    y, (cache, hl) = forward(p, x, n_in, width, depth)
+    y, (cache, hl) = forward(p, x, n_in, width, depth, q)
     R = len(t)
     e = y - np.asarray(t, float)
     loss = np.mean(e * e)
@@ -112,8 +121,8 @@ def loss_and_grad(p, x, t, n_in, width, depth):
     grads = []
     for (W, b), (h_in, z) in zip(reversed(layers), reversed(cache)):
         dz = dh * gelu_grad(z)
-        grads.append((h_in.T @ dz, dz.sum(axis=0)))
-        dh = dz @ W.T
+        grads.append((q(h_in).T @ q(dz), dz.sum(axis=0)))
+        dh = q(dz) @ q(W).T
     parts = []
     for gW, gb in reversed(grads):
         parts += [gW.reshape(-1), gb]

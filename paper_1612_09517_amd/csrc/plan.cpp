@@ -28,10 +28,12 @@ SystemSpec make_spec(int N1, int N2, const int32_t *two_I, const double *a_mT, d
   return s;
 }
 
-SystemSpec tile_order(const SystemSpec &s) {
+SystemSpec tile_order(const SystemSpec &s, bool high_first) {
   std::vector<int> idx(s.N());
   for (int k = 0; k < s.N(); ++k) idx[k] = k;
-  std::stable_sort(idx.begin(), idx.end(), [&](int x, int y) { return s.two_I[x] < s.two_I[y]; });
+  std::stable_sort(idx.begin(), idx.end(), [&](int x, int y) {
+    return high_first ? s.two_I[x] > s.two_I[y] : s.two_I[x] < s.two_I[y];
+  });
   SystemSpec o = s;
   for (int k = 0; k < s.N(); ++k) {
     o.two_I[k] = s.two_I[idx[k]];

@@ -55,9 +55,10 @@ SystemSpec make_spec(int N1, int N2, const int32_t *two_I, const double *a_mT, d
                      double kS, double kT, double T, double gamma);
 
 // The same system with its nuclei reordered for the tiled kernels: spin-1/2 nuclei first
-// (power-of-two strides), then the others by increasing 2I.  Radical flags and the caller's
-// indices travel with each nucleus; the physics does not depend on the order.
-SystemSpec tile_order(const SystemSpec &s);
+// (power-of-two strides), then the others by increasing 2I; with high_first, by decreasing
+// 2I instead (higher spins on the fastest axes, for the mixed-radix kernel).  Radical flags
+// and the caller's indices travel with each nucleus; the physics does not depend on the order.
+SystemSpec tile_order(const SystemSpec &s, bool high_first = false);
 
 // J_0(x)..J_nmax(x), x >= 0, Miller backward recurrence with the normalisation
 // J_0 + 2 sum_k J_2k = 1.

@@ -1380,7 +1380,7 @@ static int read_opts(const rp_opts *o, Opts &out) {
     if (o->max_growth != 0 && !(o->max_growth >= 2.0)) return fail(RP_EINVAL, "max_growth must be >= 2");
     const int known =
         RP_FLAG_PROFILE | RP_FLAG_TILED | RP_FLAG_XCD_LOCAL | RP_FLAG_XCD_SPREAD | RP_FLAG_NO_GRAPH | RP_FLAG_ARNOLDI |
-        RP_FLAG_TERM_SCALAR;
+        RP_FLAG_TERM_SCALAR | RP_FLAG_AXES_HIGH_FIRST;
     if ((o->flags & ~known) != 0) return fail(RP_EINVAL, "unknown flags");
     if (o->krylov_dim != 0 && (o->krylov_dim < 2 || o->krylov_dim > 32))
       return fail(RP_EINVAL, "krylov_dim must be 0 or in [2, 32]");
@@ -2201,7 +2201,8 @@ static int propagate_chebyshev(const rp_system *sys, int n_sys, const double *B_
   for (int i = 0; i < n_sys; ++i) {
     const rp_system *s = &sys[i];
     SystemSpec spec = tile_order(make_spec(s->n_nuc[0], s->n_nuc[1], s->two_I, s->a_mT, s->J_mT, s->kS, s->kT,
-                                           s->T_us, gamma_of(s)));
+                                           s->T_us, gamma_of(s)),
+                                 (op.flags & RP_FLAG_AXES_HIGH_FIRST) != 0);
     const double *ang = angles ? angles + aoffs[i] : nullptr;
     if (!(op.flags & RP_FLAG_TILED) && !log.on && !ps_t && spec.Z <= zmax) {
       res.specs.push_back(spec);
@@ -2953,7 +2954,8 @@ extern "C" int rp_propagate(const rp_system *sys, int32_t n_sys, const double *B
       const rp_system *s = &sys[i];
       const int N = s->n_nuc[0] + s->n_nuc[1];
       SystemSpec spec = tile_order(make_spec(s->n_nuc[0], s->n_nuc[1], s->two_I, s->a_mT, s->J_mT, s->kS, s->kT,
-                                             s->T_us, gamma_of(s)));
+                                             s->T_us, gamma_of(s)),
+                                   (op.flags & RP_FLAG_AXES_HIGH_FIRST) != 0);
       const double *ang = angles ? angles + aoff : nullptr;
       double *out = phi + (int64_t)i * nB * M;
       rc = op.precision == 64 ? sia_system<double>(spec, B_mT + (int64_t)i * nB, nB, ang, M, op, out, st)

@@ -49,6 +49,7 @@ RP_FLAG_XCD_SPREAD = 8
 RP_FLAG_NO_GRAPH = 16
 RP_FLAG_ARNOLDI = 32
 RP_FLAG_TERM_SCALAR = 64
+RP_FLAG_AXES_HIGH_FIRST = 128
 
 
 def lib():
@@ -158,7 +159,7 @@ def sample(system: SpinSystem, seed, M, first=0, stream_id=0, basis_mode=0, out=
 
 def propagate(systems, B_mT, angles, M, precision=64, init_mode=0, tol=0.0, rdt=0.0, r_scale=0.0,
               workspace_bytes=0, out=None, profile=False, tiled=False, xcd=None, graph=True, max_growth=0.0,
-              arnoldi=False, krylov_dim=0, term_scalar=False, ps_t_len=0, static=False):
+              arnoldi=False, krylov_dim=0, term_scalar=False, ps_t_len=0, static=False, axes_high_first=False):
     """rp_propagate: single-wavepacket yields [n_sys][nB][M] (float64 CUDA tensor).
     With ``static`` the call goes to rp_propagate_static (no device allocation inside the
     library: its static workspace area instead).
@@ -183,6 +184,7 @@ def propagate(systems, B_mT, angles, M, precision=64, init_mode=0, tol=0.0, rdt=
     flags = (RP_FLAG_PROFILE if profile else 0) | (RP_FLAG_TILED if tiled else 0)
     flags |= (0 if graph else RP_FLAG_NO_GRAPH) | (RP_FLAG_ARNOLDI if arnoldi else 0)
     flags |= RP_FLAG_TERM_SCALAR if term_scalar else 0
+    flags |= RP_FLAG_AXES_HIGH_FIRST if axes_high_first else 0
     if xcd == "local":
         flags |= RP_FLAG_XCD_LOCAL
     elif xcd == "spread":

@@ -2,7 +2,7 @@
 workload of 256 uneven systems (N ~ U{8..18} spin-1/2, a ~ N(0, 0.7) mT, kS, kT log-uniform on
 [0.1, 5] /us): the first system of every size N = 8..18 (Z = 2^8 .. 2^18), at the first and
 last of its 32 fields (0 and 5 mT), samples 0 and 1 of its seeded directions.  Systems with
-N <= 10 keep their own horizon T = min(10 / min(kS, kT), 20) us; the larger ones are cut to
+N <= 12 keep their own horizon T = min(10 / min(kS, kT), 20) us; the larger ones are cut to
 T = 0.5 us (about ten Chebyshev steps) so that the oracle finishes.  Source: the oracle's sparse
 augmented-system route only.  Run from the repository root:
 
@@ -32,7 +32,7 @@ def subset():
     first = {}
     for i, s in enumerate(w.systems):
         first.setdefault(s.N, i)
-    return [(first[N], w.systems[first[N]].T_us if N <= 10 else T_CUT) for N in sorted(first)]
+    return [(first[N], w.systems[first[N]].T_us if N <= 12 else T_CUT) for N in sorted(first)]
 
 
 def one(task):

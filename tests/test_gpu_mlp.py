@@ -1,9 +1,13 @@
 """GPU checks of the control-variate network and estimator against the FP64 oracle.
 
 Tolerances for the network: every hidden-layer product rounds its inputs to BF16
-(relative rounding error <= 2^-9 per input), so layer outputs carry relative errors of a
-few 1e-3; after three hidden layers we require a relative L2 error below 3e-2 for outputs
-and 5e-2 for gradients.  Elementwise FP32 steps (features, Adam) are checked at 1e-6."""
+(relative rounding error <= 2^-9 per input).  Against the plain FP64 oracle, layer outputs
+carry relative errors of a few 1e-3, so after three hidden layers the outputs are checked at
+a relative L2 error of 3e-2 and the gradient at 5e-2.  With the same operand rounding modelled
+in the test (the oracle's operand map), every output and every gradient element of every
+parameter block agrees to 1e-5 of its own size plus its block's largest element (measured:
+2e-7; what is left is FP32 accumulation order).  Elementwise FP32 steps (features, Adam) are
+checked at 1e-6."""
 import math
 import sys
 
@@ -100,6 +104,52 @@ def test_gradient_and_adam_match_oracle():
     gg = G.cpu().numpy().astype(float)
     want, _, _ = mlp.adam(p.astype(np.float32).astype(float), np.zeros(len(p)), np.zeros(len(p)), gg, 1, 1e-3)
     assert np.max(np.abs(P.cpu().numpy() - want)) < 1e-6
+
+
+def _bf16(a):
+    """Round to BF16 (nearest, ties to even) through FP32, as the device rounds MFMA operands."""
+    u = np.ascontiguousarray(np.asarray(a, np.float64).astype(np.float32)).view(np.uint32).astype(np.uint64)
+    u = (u + 0x7FFF + ((u >> 16) & 1)) & 0xFFFF0000
+    return u.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+def _blocks(v, n_in, width, depth):
+    """Packed parameter vector -> named blocks (W_l, b_l, w_out, b_out)."""
+    layers, w, bo = mlp.unpack(v, n_in, width, depth)
+    out = {}
+    for l, (W, b) in enumerate(layers):
+        out[f"W{l}"], out[f"b{l}"] = W, b
+    out["w_out"], out["b_out"] = w, np.array([bo])
+    return out
+
+
+def test_forward_and_gradient_elementwise_with_bf16_operands():
+    """Elementwise parity of the network with the FP64 oracle when the test rounds the operands
+    of every hidden-layer product to BF16 as the device does (everything else FP64 in the
+    oracle, FP32 on the device): outputs and every parameter block of the gradient (W_l, b_l,
+    output weights and bias) separately, each element within 1e-5 of its own size plus its
+    block's largest element.  A sign flip or a wrong block would fail by O(1)."""
+    n_in, width, depth = 19, 64, 3
+    p = _net(n_in, width, depth, seed=4).astype(np.float32).astype(float)
+    rng = np.random.default_rng(3)
+    x = rng.normal(0, 1, (96, mlp.in_pad(n_in))).astype(np.float32).astype(float)
+    t = rng.normal(0, 1, 96).astype(np.float32).astype(float)
+    _say("mlp elementwise with BF16 operands")
+    y = rp.mlp_forward(_t(p), _t(x), n_in, width, depth).cpu().numpy()
+    want_y, _ = mlp.forward(p, x, n_in, width, depth, q=_bf16)
+    dev = np.abs(y - want_y) / (np.abs(want_y) + np.abs(want_y).max())
+    _say("  forward: max scaled deviation", dev.max())
+    assert dev.max() < 1e-5
+    P, Mo, V = _t(p), torch.zeros(len(p), device="cuda"), torch.zeros(len(p), device="cuda")
+    G = torch.empty(len(p), device="cuda")
+    rp.mlp_train_step(P, Mo, V, 1, _t(x), _t(t), n_in, width, depth, lr=0.0, grad_out=G)
+    _, g = mlp.loss_and_grad(p, x, t, n_in, width, depth, q=_bf16)
+    got, want = _blocks(G.cpu().numpy(), n_in, width, depth), _blocks(g, n_in, width, depth)
+    for name in want:
+        a, b = got[name], want[name]
+        dev = np.abs(a - b) / (np.abs(b) + np.abs(b).max())
+        _say(f"  gradient block {name}: max scaled deviation {dev.max():.2e}")
+        assert dev.max() < 1e-5, name
 
 
 def test_training_reduces_loss():

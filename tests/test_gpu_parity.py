@@ -244,6 +244,9 @@ def test_reordered_axes_spin1_first():
     for prec in (64, 32):
         phi = rp.propagate(s, B, ang, 3, precision=prec).cpu().numpy()[0]
         assert _rel(phi, want) < TOL[prec], _rel(phi, want)
+        # the other axis order (spin-1 nuclei on the fastest axes, mixed-radix kernel)
+        high = rp.propagate(s, B, ang, 3, precision=prec, axes_high_first=True).cpu().numpy()[0]
+        assert _rel(high, want) < TOL[prec], _rel(high, want)
 
 
 def test_pair_term_kernel_matches_scalar_term_kernel():
@@ -373,9 +376,10 @@ def test_autotuner_picks_valid_parameters_and_caches(tmp_path):
     _say("autotune")
     best = autotune.tune(s, B, precision=32, samples=4, cache=cache)
     assert best["rdt"] in autotune.RDT and best["xcd"] in autotune.XCD
+    assert set(best) == {"rdt", "xcd", "term_scalar", "tiled"}             # Z = 1024: resident or tiled
     assert autotune.tune(s, B, precision=32, cache=cache) == best          # served from the cache
     ang = rp.sample(s, 5, 4)
-    a = rp.propagate(s, B[None, :], ang, 4, precision=32, tiled=True, **best).cpu().numpy()
+    a = rp.propagate(s, B[None, :], ang, 4, precision=32, **best).cpu().numpy()
     b = rp.propagate(s, B[None, :], ang, 4, precision=64).cpu().numpy()
     assert np.max(np.abs(a - b) / b) < 1e-5
 

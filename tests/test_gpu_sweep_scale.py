@@ -102,6 +102,32 @@ def test_full_size_short_horizon_against_oracle_golden(name):
                 assert abs(phi[b, i] - want) < tol * want, (name, prec, Bv, i, phi[b, i], want)
 
 
+def test_batched_subset_against_oracle_golden():
+    """A subset of the batched workload of 256 uneven systems: the first system of every size
+    N = 8..18 (Z = 2^8 .. 2^18, one per size class), each with its own rates, horizon and
+    fields, all in ONE call -- the LDS-resident launches for the small ones and one job queue
+    of unequal Z for the tiled ones -- against yields the oracle computed one by one
+    (tests/golden/make_batched_golden.py; systems beyond N = 12 on a horizon cut to 0.5 us)."""
+    import dataclasses
+    g = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "batched_golden.json")))
+    w = workloads.batched_c3()
+    systems = [dataclasses.replace(w.systems[e["index"]], T_us=e["T_us"]) for e in g["systems"]]
+    B = np.array([e["fields_mT"] for e in g["systems"]])
+    M = max(g["samples"]) + 1
+    ang = torch.cat([rp.sample(s, w.seed, M).reshape(-1) for s in systems])
+    for prec, tol in ((64, 1e-10), (32, 1e-5)):
+        print("batched subset: precision", prec, "Z =", [s.Z for s in systems], flush=True)
+        phi = rp.propagate(systems, B, ang, M, precision=prec).cpu().numpy()
+        worst = 0.0
+        for i, e in enumerate(g["systems"]):
+            for b, Bv in enumerate(e["fields_mT"]):
+                for j in g["samples"]:
+                    want = g["phi"][f"{e['index']}:{Bv}:{j}"]
+                    worst = max(worst, abs(phi[i, b, j] - want) / want)
+                    assert abs(phi[i, b, j] - want) < tol * want, (prec, e["N"], Bv, j, phi[i, b, j], want)
+        print("  max relative error", worst, flush=True)
+
+
 def test_maximum_state_against_oracle_golden():
     """The largest state of the checks, Z = 2^23 (12+11 spin-1/2; 256 MB per complex-FP32
     wavepacket, 32,768 workgroups per launch), against the oracle's per-radical route

@@ -187,3 +187,19 @@ def test_bench_refuses_more_than_one_gpu():
     r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
                        text=True, timeout=120)
     assert r.returncode == 2 and "one GPU only" in r.stdout
+
+
+def test_autotune_dimensions_follow_the_system():
+    """The tuner searches only the choices that exist for a system: the tile kernel's index pairs
+    need complex FP32 and 8 leading spin-1/2 nuclei; the LDS-resident path needs a small state;
+    the axis order matters only when spins are mixed."""
+    from paper_1612_09517_amd import autotune
+    big = SpinSystem(7, 7, [1] * 14, [0.1] * 14)
+    small = SpinSystem(4, 4, [1] * 8, [0.1] * 8)
+    mixed = SpinSystem(5, 5, [2] + [1] * 9, [0.1] * 10)
+    names = lambda s, p: [n for n, _ in autotune.dimensions(s, p)]
+    assert names(big, 32) == ["xcd", "term_scalar"]
+    assert names(big, 64) == ["xcd"]
+    assert names(small, 32) == ["xcd", "term_scalar", "tiled"]
+    assert names(small, 64) == ["xcd", "tiled"]
+    assert names(mixed, 32) == ["xcd", "term_scalar", "axes_high_first"]
