@@ -693,7 +693,7 @@ def main():
                     help="device workspace cap per call (bounds how many wavepackets run together)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe", type=float, default=0.0,
-                    help="only copy a buffer of this many GiB three times (calibrates HBM counters)")
+                    help="only run the streaming probes over buffers of this many GiB (ceilings; calibrates counters)")
     ap.add_argument("--workload", default="sweep",
                     choices=["sweep", "tiny", "batched", "large", "paper", "trace", "sampling", "arnoldi",
                              "histogram"])
@@ -753,14 +753,11 @@ def main():
         other_workload(args)
         return
     if args.copy_probe > 0:
-        import torch
-        n = int(args.copy_probe * 2 ** 30) // 4
-        src = torch.ones(n, dtype=torch.float32, device="cuda")
-        dst = torch.empty_like(src)
-        for _ in range(3):
-            dst.copy_(src)
-        torch.cuda.synchronize()
-        print(json.dumps({"copy_probe_bytes_each_way": 4 * n, "copies": 3}), flush=True)
+        # hand-written 16-byte streaming kernels (rp_probe_stream): GB/s per pattern; under
+        # rocprofv3 --pmc the copy launches (k_stream<0>, GiB read and written) calibrate the counters
+        from paper_1612_09517_amd import rp
+        n = int(args.copy_probe * 2 ** 30)
+        print(json.dumps({"probe_bytes": n, "GBps": rp.probe_stream(n, reps=5)}), flush=True)
         return
     if args.gpus != 1:
         print(json.dumps({"error": "bench.py measures one GPU only (--gpus 1); a multi-GPU sweep would "
@@ -816,6 +813,8 @@ def main():
         bpe = p["bytes_per_element"]
         nterms = p["terms_per_step"]
     achieved = prof["elements"] * bpe / (prof["term_ms"] * 1e-3) / 1e9
+    ceil = rp.probe_stream(1 << 30, reps=5)
+    say(f"streaming ceilings (GB/s): {ceil}")
     rec = {
         "metric": "sweep wall time at sigma(Phi_S)<=1e-3 vs plain FP64 MC; H.psi HBM GB/s vs peak",
         "value": value,
@@ -845,6 +844,8 @@ def main():
                      "avg_launch_us": prof["term_ms"] * 1e3 / max(prof["term_launches"], 1),
                      "bytes_per_element_term": bpe, "terms_per_step": nterms,
                      "profiled_steps": args.profile_steps,
+                     "measured_ceilings_GBps": {k: round(v, 1) for k, v in ceil.items()},
+                     "frac_of_read2_write1": achieved / ceil["read2_write1"],
                      "term_time_frac": prof["term_ms"] / max(prof["total_ms"], 1e-9),
                      "quad_time_frac": prof["quad_ms"] / max(prof["total_ms"], 1e-9)},
     }

@@ -342,6 +342,17 @@ int rp_combine(const double *mean_a, const double *err_a, const double *mean_b, 
  */
 int rp_cv_beta(const double *phi, const double *g, int32_t nB, int64_t M, double *beta, void *hip_stream);
 
+/*
+ * rp_probe_stream -- measurement helper: the practical HBM ceilings the term kernel is quoted
+ * against.  Times `reps` launches (after one warm-up) of a plain streaming kernel over
+ * `bytes` bytes (a multiple of 16) with 16-byte vector accesses, on hip_stream, and waits for
+ * them.  kind 0: c = a (reads and writes `bytes` each); 1: c = a + b (two reads, one write);
+ * 2: reads a only; 3: writes c only.  a, b, c: device buffers of `bytes` bytes (b only for
+ * kind 1, a not for kind 3).  *ms_per_launch (host) receives the average launch time.
+ */
+int rp_probe_stream(int32_t kind, const void *a, const void *b, void *c, int64_t bytes, int32_t reps,
+                    double *ms_per_launch, void *hip_stream);
+
 /* Static text for a return code. */
 const char *rp_strerror(int code);
 

@@ -24,7 +24,8 @@ def hipcc():
 
 def build(verbose=False):
     """Compiles every source into librp.so (always rebuilds)."""
-    srcs = [os.path.join(CSRC, "rp.hip"), os.path.join(CSRC, "mlp.hip"), os.path.join(CSRC, "plan.cpp")]
+    srcs = [os.path.join(CSRC, "rp.hip"), os.path.join(CSRC, "mlp.hip"), os.path.join(CSRC, "probe.hip"),
+            os.path.join(CSRC, "plan.cpp")]
     tmp = LIB + ".tmp"
     cmd = [hipcc()] + HIP_FLAGS + ["-shared", "-I", INCLUDE, "-I", CSRC] + srcs + ["-o", tmp]
     if verbose:

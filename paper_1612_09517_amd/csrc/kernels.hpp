@@ -139,6 +139,7 @@ struct FinArgs {
   const double *dt;        // [fields]
   int32_t *stepc;          // [jobs] steps finalised so far (read, then incremented)
   const QJob *jobs;        // job queue (several systems), or null: nbx tiles per job
+  const int32_t *slots;    // job queue: slot of each workgroup (occupied slots), or null
   const double *sys_k;     // job queue: [systems][2] = (kS, k_min)
   int64_t nbx;
   int32_t njobs;

@@ -19,6 +19,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <map>
+#include <tuple>
 #include <mutex>
 #include <numeric>
 #include <string>
@@ -234,8 +235,8 @@ struct InitArgs {
   cx<R> *psi;                   // [jobs][4Z]
   const cx<double> *tab;        // [M][N][5]
   const int32_t *job_sample;    // [jobs]
-  const int32_t *tile_job;      // job queue (several systems): tile -> job
-  const QJob *jobs;             // job queue: descriptors (offsets, coherent-table row)
+  const int32_t *init_map;      // job queue: [tiles][2] = (slot, tile within the slot)
+  const QJob *jobs;             // job queue: slot descriptors (offsets, coherent-table row)
   const SysArgs<R> *systab;     // job queue: systems
   int64_t Z;
   int64_t nbx;
@@ -255,10 +256,10 @@ __global__ __launch_bounds__(256) void k_init(InitArgs<R> a) {
   int N;
   const int32_t *stride, *d;
   if constexpr (Q) {
-    const int64_t job = a.tile_job[L];
+    const int64_t job = a.init_map[2 * L];
     const QJob &j = a.jobs[job];
     const SysArgs<R> &sa = a.systab[j.sys];
-    M = (L - j.blk) * kBlock + threadIdx.x;
+    M = (int64_t)a.init_map[2 * L + 1] * kBlock + threadIdx.x;
     Z = j.Z;
     off = j.vec;
     t = a.tab + j.tab * (RP_MAX_TWO_I + 1);
@@ -1163,7 +1164,7 @@ __global__ __launch_bounds__(MAXB) void k_resident(ResArgs<R> ra) {
 // One workgroup per job: sums the per-workgroup partials of the quadrature and of the norm.
 __global__ __launch_bounds__(256) void k_finalize(FinArgs fa) {
   __shared__ double lds[4];
-  const int64_t job = blockIdx.x;
+  const int64_t job = fa.slots ? fa.slots[blockIdx.x] : blockIdx.x;
   int64_t b0 = job * fa.nbx, nb = fa.nbx;
   int fi;
   double kS = fa.kS, kmin = fa.kmin;
@@ -1195,6 +1196,26 @@ __global__ __launch_bounds__(256) void k_finalize(FinArgs fa) {
   const double Nt = decay * nrm;           // population N(t_j) of the wavepacket
   if (!(Nt <= fa.prev_norm[job] * (1.0 + fa.rtol) + 1e-300) || !(y == y)) atomicOr(fa.flag, 1);
   fa.prev_norm[job] = Nt;
+}
+
+// Job queue: clears the sums of the slots that take new jobs.
+__global__ __launch_bounds__(256) void k_slots_reset(const int32_t *slots, int64_t n, double *phi, double *prev,
+                                                     int32_t *stepc) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int32_t s = slots[i];
+  phi[s] = 0.0;
+  prev[s] = 1.0 + 1e-6;
+  stepc[s] = 0;
+}
+
+// Job queue: writes the yields of the slots whose jobs have done their steps.
+__global__ __launch_bounds__(256) void k_slots_scatter(const int32_t *slots, int64_t n, const double *phi,
+                                                       const int64_t *dst, double *out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int32_t s = slots[i];
+  out[dst[s]] = phi[s];
 }
 
 __global__ __launch_bounds__(256) void k_fill(double *p, int64_t n, double v) {
@@ -1518,20 +1539,25 @@ struct TiledSys {
 };
 
 // Tiled propagation of every (system, field, sample) job of a group of systems that share a
-// term kernel.  Jobs are ordered by decreasing step count, so the jobs still running at any
-// step form a prefix; consecutive jobs form chunks that fit the workspace and are propagated
-// together, one launch per Chebyshev term.  A chunk whose jobs all belong to one system uses
-// the kernels' uniform form (job = tile / nbx, system constants in the kernel arguments); a
-// chunk mixing systems of unequal Z uses the job queue (per-tile job index, per-job offsets,
-// per-system constants in a table).
+// term kernel, as a persistent job queue.  The workspace holds a fixed set of slots, one
+// wavepacket each; the slots of one nuclear-state count Z form a pool.  Every Chebyshev term
+// is one launch over the tiles of all occupied slots, whatever their Z.  When a job has done
+// its steps, its yield is written out and the next job of the pool's queue (longest first)
+// takes the slot, starting at its own step 0, so the launches stay full until the queues
+// drain.  The host knows every job's step count, so it updates the slot tables between steps
+// without waiting for the device.  Pools get slots in proportion to the steps their jobs need,
+// so that they drain together.  While the occupied slots are a prefix of one system's pool the
+// kernels run in their uniform form (job = tile / nbx, system constants in the kernel
+// arguments); otherwise per tile they read the slot index and the slot's descriptor (offsets,
+// field, coherent-state row) and the system's constants from a table.
 template <typename R>
 struct TiledRun {
   struct Job {
     int32_t sys, field, sample;
   };
-  struct Chunk {
-    int64_t j0 = 0, nj = 0, sZ = 0, tiles = 0;
-    bool queue = false;
+  struct Pool {
+    int64_t Z = 0, nbx = 0, slots = 0, slot0 = 0;
+    std::vector<int64_t> queue;   // job indices, decreasing step count
   };
   std::vector<TiledSys> sys;
   int nB = 0;
@@ -1545,30 +1571,47 @@ struct TiledRun {
   std::vector<SysArgs<R>> sargs;
   int64_t tab_rows = 0;
   std::vector<Job> jobs;
-  std::vector<Chunk> chunks;
-  int64_t max_nj = 0, max_sZ = 0, max_tiles = 0;
+  std::vector<Pool> pools;
+  int64_t n_slots = 0, slot_states = 0, slot_tiles = 0;   // slots, sum of their Z and of their tiles
   int64_t fixed_bytes = 0, chunk_bytes = 0;
 
-  int64_t Zof(const Job &j) const { return sys[j.sys].spec.Z; }
   static int64_t nbx_of(int64_t Z) { return (Z + kBlock - 1) / kBlock; }
-  int64_t chunk_size(int64_t nj, int64_t sZ, int64_t tiles) const {
+  int64_t slots_size(int64_t ns, int64_t sZ, int64_t tiles) const {
     Sizer z;
     for (int b = 0; b < 3; ++b) z.add<cx<R>>(4 * sZ);       // psi / phi_even, phi_odd, accumulator
     z.add<cx<R>>((int64_t)nt * sZ);                          // singlet amplitudes of one step
     z.add<double>(tiles);                                    // norm partials
     z.add<double>(2 * tiles);                                // quadrature partials
-    z.add<int32_t>(tiles);                                   // tile -> job
-    z.add<double>(nj);                                       // phi
-    z.add<double>(nj);                                       // previous norm
-    z.add<int32_t>(nj);                                      // steps done
-    z.add<int32_t>(nj);                                      // field of each job
-    z.add<int32_t>(nj);                                      // sample of each job
-    z.add<int64_t>(nj);                                      // output index
-    z.add<QJob>(nj);
+    z.add<int32_t>(tiles);                                   // tile -> slot of the term launches
+    z.add<int32_t>(2 * tiles);                               // (slot, tile) of the initialisation launches
+    z.add<double>(ns);                                       // phi
+    z.add<double>(ns);                                       // previous norm
+    z.add<int32_t>(ns);                                      // steps done
+    z.add<int32_t>(ns);                                      // field of each slot's job
+    z.add<int64_t>(ns);                                      // output index
+    z.add<QJob>(ns);
+    for (int l = 0; l < 3; ++l) z.add<int32_t>(ns);          // occupied, finished and refilled slots
     return z.used;
   }
 
-  // budget: bytes for the chunk buffers, and for the tables too when tables_in_budget.
+  // Slots per pool for a total of E nuclear states (at least one per pool, at most its jobs),
+  // in proportion to the steps of each pool's jobs.
+  void assign_slots(double E, const std::vector<double> &steps) {
+    double denom = 0.0;
+    for (size_t p = 0; p < pools.size(); ++p) denom += steps[p] * (double)pools[p].Z;
+    for (size_t p = 0; p < pools.size(); ++p) {
+      const double want = E * steps[p] / std::max(denom, 1.0);
+      pools[p].slots = std::max<int64_t>(1, std::min<int64_t>((int64_t)pools[p].queue.size(), (int64_t)want));
+    }
+    n_slots = slot_states = slot_tiles = 0;
+    for (auto &p : pools) {
+      p.slot0 = n_slots;
+      n_slots += p.slots;
+      slot_states += p.slots * p.Z;
+      slot_tiles += p.slots * p.nbx;
+    }
+  }
+
   int prepare(const Opts &op, int64_t budget, bool tables_in_budget, bool default_chunks) {
     const int ns = (int)sys.size();
     std::vector<const SystemSpec *> specs;
@@ -1631,13 +1674,32 @@ struct TiledRun {
         nsteps[g] = p.n_steps;
       }
     }
-    // Jobs by decreasing step count (stable: system, field, sample order among equals).
+    // Jobs, and one queue per nuclear-state count, longest first (stable among equals:
+    // system, field, sample order).
     jobs.clear();
     for (int s = 0; s < ns; ++s)
       for (int b = 0; b < nB; ++b)
         for (int64_t m = 0; m < M; ++m) jobs.push_back({s, s * nB + b, (int32_t)m});
-    std::stable_sort(jobs.begin(), jobs.end(),
-                     [&](const Job &a, const Job &b) { return nsteps[a.field] > nsteps[b.field]; });
+    std::vector<int64_t> order(jobs.size());
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int64_t a, int64_t b) { return nsteps[jobs[a].field] > nsteps[jobs[b].field]; });
+    pools.clear();
+    std::map<int64_t, size_t> pool_of;
+    for (int64_t j : order) {
+      const int64_t Z = sys[jobs[j].sys].spec.Z;
+      auto it = pool_of.find(Z);
+      if (it == pool_of.end()) {
+        it = pool_of.emplace(Z, pools.size()).first;
+        pools.emplace_back();
+        pools.back().Z = Z;
+        pools.back().nbx = nbx_of(Z);
+      }
+      pools[it->second].queue.push_back(j);
+    }
+    std::vector<double> steps(pools.size(), 0.0);
+    for (size_t p = 0; p < pools.size(); ++p)
+      for (int64_t j : pools[p].queue) steps[p] += (double)nsteps[jobs[j].field];
     Sizer f;
     f.add<FieldDev<R>>(nG);
     f.add<cx<R>>((int64_t)coef.size());
@@ -1648,49 +1710,29 @@ struct TiledRun {
     f.add<cx<double>>(tab_rows * (RP_MAX_TWO_I + 1));
     fixed_bytes = f.used;
     const int64_t region = tables_in_budget ? budget - fixed_bytes : budget;
-    // Chunks: consecutive jobs while the workspace allows; by default the chunk's three
-    // wavepacket buffers stay within 192 MB (resident in the 256 MB Infinity Cache across
-    // launches) unless that leaves fewer than 64 jobs; fewer than 2^24 workgroups per launch.
-    chunks.clear();
-    max_nj = max_sZ = max_tiles = 0;
-    const int64_t vec_cap = (int64_t)192 << 20;
-    Chunk c;
-    for (int64_t j = 0; j < (int64_t)jobs.size(); ++j) {
-      const int64_t Z = Zof(jobs[j]), nbx = nbx_of(Z);
-      const int64_t nj = c.nj + 1, sZ = c.sZ + Z, tiles = c.tiles + nbx;
-      bool fits = chunk_size(std::max(max_nj, nj), std::max(max_sZ, sZ), std::max(max_tiles, tiles)) <= region &&
-                  tiles < ((int64_t)1 << 24);
-      if (default_chunks && c.nj >= 64 && 3 * 4 * sZ * (int64_t)sizeof(cx<R>) > vec_cap) fits = false;
-      if (!fits && c.nj == 0)
+    // Slots: by default the three wavepacket buffers take about 192 MB (resident in the 256 MB
+    // Infinity Cache across launches) or 64 wavepackets of the typical size, whichever is
+    // more; then as many as the workspace holds, and fewer than 2^24 tiles per launch.
+    double typical = 0.0, wsum = 0.0;
+    for (size_t p = 0; p < pools.size(); ++p) {
+      typical += steps[p] * (double)pools[p].Z;
+      wsum += steps[p];
+    }
+    typical /= std::max(wsum, 1.0);
+    double E = std::max((double)(((int64_t)192 << 20) / (12 * (int64_t)sizeof(cx<R>))), 64.0 * typical);
+    if (!default_chunks) E = 1e30;
+    assign_slots(E, steps);
+    while (slots_size(n_slots, slot_states, slot_tiles) > region || slot_tiles >= ((int64_t)1 << 24)) {
+      bool all_one = true;
+      for (auto &p : pools) all_one = all_one && p.slots == 1;
+      if (all_one)
         return fail(RP_ENOMEM, "workspace of " + std::to_string(budget) + " bytes is too small for one wavepacket of " +
-                                   std::to_string(Z) + " nuclear states (needs " +
-                                   std::to_string(fixed_bytes + chunk_size(1, Z, nbx)) + ")");
-      if (!fits) {
-        chunks.push_back(c);
-        max_nj = std::max(max_nj, c.nj);
-        max_sZ = std::max(max_sZ, c.sZ);
-        max_tiles = std::max(max_tiles, c.tiles);
-        c = Chunk();
-        c.j0 = j;
-        --j;
-        continue;
-      }
-      c.nj = nj;
-      c.sZ = sZ;
-      c.tiles = tiles;
+                                   "each of " + std::to_string(pools.size()) + " state sizes (needs " +
+                                   std::to_string(fixed_bytes + slots_size(n_slots, slot_states, slot_tiles)) + ")");
+      E = std::min(E, (double)slot_states) * 0.9;
+      assign_slots(E, steps);
     }
-    if (c.nj) {
-      chunks.push_back(c);
-      max_nj = std::max(max_nj, c.nj);
-      max_sZ = std::max(max_sZ, c.sZ);
-      max_tiles = std::max(max_tiles, c.tiles);
-    }
-    for (auto &ch : chunks) {
-      ch.queue = false;
-      for (int64_t j = ch.j0 + 1; j < ch.j0 + ch.nj; ++j)
-        if (jobs[j].sys != jobs[ch.j0].sys) ch.queue = true;
-    }
-    chunk_bytes = chunk_size(max_nj, max_sZ, max_tiles);
+    chunk_bytes = slots_size(n_slots, slot_states, slot_tiles);
     // Block order: a wavepacket that fits an XCD's 4 MB L2 comfortably is given to one XCD
     // (its partner tiles stay in that L2); larger ones are spread over all XCDs, so that the
     // whole GPU works on few wavepackets at a time and far partners hit the Infinity Cache.
@@ -1712,18 +1754,21 @@ struct TiledRun {
     double *dK = ar.take<double>(2 * ns);
     cx<double> *dTab = ar.take<cx<double>>(tab_rows * (RP_MAX_TWO_I + 1));
     cx<R> *bufs[3];
-    for (int b = 0; b < 3; ++b) bufs[b] = ar.take<cx<R>>(4 * max_sZ);
-    cx<R> *D = ar.take<cx<R>>((int64_t)nt * max_sZ);
-    double *dPn = ar.take<double>(max_tiles);
-    double *dPq = ar.take<double>(2 * max_tiles);
-    int32_t *dTileJob = ar.take<int32_t>(max_tiles);
-    double *dPhi = ar.take<double>(max_nj);
-    double *dPrev = ar.take<double>(max_nj);
-    int32_t *dStep = ar.take<int32_t>(max_nj);
-    int32_t *dJf = ar.take<int32_t>(max_nj);
-    int32_t *dJs = ar.take<int32_t>(max_nj);
-    int64_t *dDst = ar.take<int64_t>(max_nj);
-    QJob *dJobs = ar.take<QJob>(max_nj);
+    for (int b = 0; b < 3; ++b) bufs[b] = ar.take<cx<R>>(4 * slot_states);
+    cx<R> *D = ar.take<cx<R>>((int64_t)nt * slot_states);
+    double *dPn = ar.take<double>(slot_tiles);
+    double *dPq = ar.take<double>(2 * slot_tiles);
+    int32_t *dTileJob = ar.take<int32_t>(slot_tiles);
+    int32_t *dInitMap = ar.take<int32_t>(2 * slot_tiles);
+    double *dPhi = ar.take<double>(n_slots);
+    double *dPrev = ar.take<double>(n_slots);
+    int32_t *dStep = ar.take<int32_t>(n_slots);
+    int32_t *dJf = ar.take<int32_t>(n_slots);
+    int64_t *dDst = ar.take<int64_t>(n_slots);
+    QJob *dJobs = ar.take<QJob>(n_slots);
+    int32_t *dActive = ar.take<int32_t>(n_slots);
+    int32_t *dDone = ar.take<int32_t>(n_slots);
+    int32_t *dNew = ar.take<int32_t>(n_slots);
     if (ar.overflow) return fail(RP_ENOMEM, "internal: workspace layout overflow");
     HIPCHK(hipMemcpyAsync(dF, fdev.data(), nG * sizeof(FieldDev<R>), hipMemcpyHostToDevice, st));
     HIPCHK(hipMemcpyAsync(dCoef, coef.data(), coef.size() * sizeof(cx<R>), hipMemcpyHostToDevice, st));
@@ -1756,231 +1801,266 @@ struct TiledRun {
         HIPCHK(hipGetLastError());
       }
     }
-    const double rtol = op.precision == 64 ? 1e-9 : 1e-4;
-    std::vector<int32_t> hJf, hJs, hTile;
-    std::vector<int64_t> hDst, tile_start;
-    std::vector<QJob> hJobs;
-    for (const Chunk &ch : chunks) {
-      const int64_t nj = ch.nj;
-      const int s0 = jobs[ch.j0].sys;
-      const SystemSpec &sp0 = sys[s0].spec;
-      // Streaming (non-temporal) loads and stores of phi_{n-1}, phi_{n+1} and the accumulator
-      // when the chunk's three wavepacket buffers exceed the 256 MB Infinity Cache: they would
-      // not survive there until the next launch anyway, and the hint leaves the L2 to the
-      // partner tiles of phi_n.  The singlet amplitudes, read only by the quadrature, always
-      // stream.
-      const bool stream_nt = 3 * 4 * ch.sZ * (int64_t)sizeof(cx<R>) > ((int64_t)256 << 20);
-      hJf.assign(nj, 0);
-      hJs.assign(nj, 0);
-      hDst.assign(nj, 0);
-      hJobs.assign(nj, QJob());
-      tile_start.assign(nj + 1, 0);
-      hTile.clear();
+    // Static slot layout: pool by pool, slot s of a pool at vec/amp offsets of its own.
+    std::vector<int32_t> slot_pool(n_slots);
+    std::vector<int64_t> slot_vec(n_slots), slot_amp(n_slots);
+    {
       int64_t vec = 0, amp = 0;
-      for (int64_t q = 0; q < nj; ++q) {
-        const Job &jb = jobs[ch.j0 + q];
-        const SystemSpec &sp = sys[jb.sys].spec;
-        const int64_t Z = sp.Z, nbx = nbx_of(Z);
-        hJf[q] = jb.field;
-        hJs[q] = jb.sample;
-        hDst[q] = sys[jb.sys].out + (int64_t)(jb.field - jb.sys * nB) * M + jb.sample;
-        QJob &qj = hJobs[q];
-        qj.sys = jb.sys;
-        qj.field = jb.field;
-        qj.nbx = (int32_t)nbx;
-        qj.pad = 0;
-        qj.Z = Z;
-        qj.vec = vec;
-        qj.amp = amp;
-        qj.blk = tile_start[q];
-        qj.tab = tab_off[jb.sys] + (int64_t)jb.sample * std::max(sp.N(), 1);
-        tile_start[q + 1] = tile_start[q] + nbx;
-        vec += 4 * Z;
-        amp += Z;
-        if (ch.queue)
-          for (int64_t b = 0; b < nbx; ++b) hTile.push_back((int32_t)q);
+      for (size_t p = 0; p < pools.size(); ++p)
+        for (int64_t q = 0; q < pools[p].slots; ++q) {
+          const int64_t s = pools[p].slot0 + q;
+          slot_pool[s] = (int32_t)p;
+          slot_vec[s] = vec;
+          slot_amp[s] = amp;
+          vec += 4 * pools[p].Z;
+          amp += pools[p].Z;
+        }
+    }
+    const bool one_system = ns == 1;
+    const int64_t Z0 = sys[0].spec.Z, nbx0 = nbx_of(Z0);
+    const SysArgs<R> &sa0 = sargs[0];
+    std::vector<int64_t> slot_job(n_slots, -1), slot_left(n_slots, 0);
+    std::vector<size_t> next(pools.size(), 0);
+    std::vector<int32_t> hJf(n_slots, 0), hTile, hInit, active, done, fresh;
+    std::vector<int64_t> hDst(n_slots, 0);
+    std::vector<QJob> hJobs(n_slots);
+    std::memset(hJobs.data(), 0, n_slots * sizeof(QJob));
+    for (int64_t s = 0; s < n_slots; ++s) {
+      const Pool &p = pools[slot_pool[s]];
+      hJobs[s].nbx = (int32_t)p.nbx;
+      hJobs[s].Z = p.Z;
+      hJobs[s].vec = slot_vec[s];
+      hJobs[s].amp = slot_amp[s];
+    }
+    // Takes the next job of slot s's pool, if any.
+    auto assign = [&](int64_t s) -> bool {
+      Pool &p = pools[slot_pool[s]];
+      size_t &k = next[slot_pool[s]];
+      if (k >= p.queue.size()) {
+        slot_job[s] = -1;
+        return false;
       }
-      HIPCHK(hipMemcpyAsync(dJf, hJf.data(), nj * 4, hipMemcpyHostToDevice, st));
-      HIPCHK(hipMemcpyAsync(dJs, hJs.data(), nj * 4, hipMemcpyHostToDevice, st));
-      HIPCHK(hipMemcpyAsync(dDst, hDst.data(), nj * 8, hipMemcpyHostToDevice, st));
-      HIPCHK(hipMemcpyAsync(dJobs, hJobs.data(), nj * sizeof(QJob), hipMemcpyHostToDevice, st));
-      if (ch.queue) HIPCHK(hipMemcpyAsync(dTileJob, hTile.data(), hTile.size() * 4, hipMemcpyHostToDevice, st));
-      const int64_t nbx0 = nbx_of(sp0.Z);
-      const SysArgs<R> &sa0 = sargs[s0];
-      // initial wavepackets
-      {
-        InitArgs<R> ia;
-        std::memset(&ia, 0, sizeof(ia));
-        ia.psi = bufs[0];
-        ia.tab = ch.queue ? dTab : dTab + tab_off[s0] * (RP_MAX_TWO_I + 1);
-        ia.job_sample = dJs;
-        ia.tile_job = dTileJob;
-        ia.jobs = dJobs;
-        ia.systab = dSys;
-        ia.Z = sp0.Z;
-        ia.nbx = nbx0;
-        ia.tiles = ch.tiles;
-        ia.njobs = (int32_t)nj;
-        ia.N = sp0.N();
-        for (int k = 0; k < sp0.N(); ++k) {
-          ia.stride[k] = sa0.stride[k];
-          ia.d[k] = sa0.d[k];
+      const int64_t j = p.queue[k++];
+      const Job &jb = jobs[j];
+      slot_job[s] = j;
+      slot_left[s] = nsteps[jb.field];
+      hJf[s] = jb.field;
+      hDst[s] = sys[jb.sys].out + (int64_t)(jb.field - jb.sys * nB) * M + jb.sample;
+      hJobs[s].sys = jb.sys;
+      hJobs[s].field = jb.field;
+      hJobs[s].tab = tab_off[jb.sys] + (int64_t)jb.sample * std::max(sys[jb.sys].spec.N(), 1);
+      return true;
+    };
+    // Starts the jobs just assigned to the slots in `fresh`: tables, cleared sums, psi_0 into
+    // buffer ipsi.
+    auto start = [&](int ipsi) -> int {
+      if (fresh.empty()) return RP_OK;
+      HIPCHK(hipMemcpyAsync(dJf, hJf.data(), n_slots * 4, hipMemcpyHostToDevice, st));
+      HIPCHK(hipMemcpyAsync(dDst, hDst.data(), n_slots * 8, hipMemcpyHostToDevice, st));
+      HIPCHK(hipMemcpyAsync(dJobs, hJobs.data(), n_slots * sizeof(QJob), hipMemcpyHostToDevice, st));
+      HIPCHK(hipMemcpyAsync(dNew, fresh.data(), fresh.size() * 4, hipMemcpyHostToDevice, st));
+      hInit.clear();
+      for (int32_t s : fresh)
+        for (int64_t b = 0; b < hJobs[s].nbx; ++b) {
+          hInit.push_back(s);
+          hInit.push_back((int32_t)b);
         }
-        if (sp0.N() == 0) {
-          ia.stride[0] = 1;
-          ia.d[0] = 1;
+      HIPCHK(hipMemcpyAsync(dInitMap, hInit.data(), hInit.size() * 4, hipMemcpyHostToDevice, st));
+      hipLaunchKernelGGL(k_slots_reset, dim3(grid1((int64_t)fresh.size())), dim3(256), 0, st, (const int32_t *)dNew,
+                         (int64_t)fresh.size(), dPhi, dPrev, dStep);
+      InitArgs<R> ia;
+      std::memset(&ia, 0, sizeof(ia));
+      ia.psi = bufs[ipsi];
+      ia.tab = dTab;
+      ia.init_map = dInitMap;
+      ia.jobs = dJobs;
+      ia.systab = dSys;
+      ia.tiles = (int64_t)hInit.size() / 2;
+      hipLaunchKernelGGL((k_init<R, true>), dim3((unsigned)ia.tiles), dim3(kBlock), 0, st, ia);
+      HIPCHK(hipGetLastError());
+      fresh.clear();
+      return RP_OK;
+    };
+    // Occupied slots in slot order; their tiles numbered in that order for the term launches.
+    auto relayout = [&]() -> int {
+      active.clear();
+      hTile.clear();
+      for (int64_t s = 0; s < n_slots; ++s)
+        if (slot_job[s] >= 0) {
+          hJobs[s].blk = (int64_t)hTile.size();
+          for (int64_t b = 0; b < hJobs[s].nbx; ++b) hTile.push_back((int32_t)s);
+          active.push_back((int32_t)s);
         }
-        if (ch.queue)
-          hipLaunchKernelGGL((k_init<R, true>), dim3((unsigned)ch.tiles), dim3(kBlock), 0, st, ia);
-        else
-          hipLaunchKernelGGL((k_init<R, false>), dim3((unsigned)ch.tiles), dim3(kBlock), 0, st, ia);
+      if (active.empty()) return RP_OK;
+      HIPCHK(hipMemcpyAsync(dJobs, hJobs.data(), n_slots * sizeof(QJob), hipMemcpyHostToDevice, st));
+      HIPCHK(hipMemcpyAsync(dTileJob, hTile.data(), hTile.size() * 4, hipMemcpyHostToDevice, st));
+      HIPCHK(hipMemcpyAsync(dActive, active.data(), active.size() * 4, hipMemcpyHostToDevice, st));
+      return RP_OK;
+    };
+    int rc;
+    int ip = 0, ia_ = 2, iodd = 1;   // psi, accumulator and odd-term buffers
+    for (int64_t s = 0; s < n_slots; ++s)
+      if (assign(s)) fresh.push_back((int32_t)s);
+    if ((rc = start(ip))) return rc;
+    if ((rc = relayout())) return rc;
+    const double rtol = op.precision == 64 ? 1e-9 : 1e-4;
+    const double eb = (double)sizeof(R) / 4.0;   // bytes per element, in units of complex-FP32 bytes
+    const int64_t slab = slot_states;
+    // Streaming (non-temporal) loads and stores of phi_{n-1}, phi_{n+1} and the accumulator
+    // when the slots' three wavepacket buffers exceed the 256 MB Infinity Cache: they would not
+    // survive there until the next launch anyway, and the hint leaves the L2 to the partner
+    // tiles of phi_n.  The singlet amplitudes, read only by the quadrature, always stream.
+    const bool stream_nt = 3 * 4 * slot_states * (int64_t)sizeof(cx<R>) > ((int64_t)256 << 20);
+    // All launches of one step over the occupied slots: Chebyshev terms, in-step quadrature,
+    // finalisation.  uniform: the occupied slots are slots 0 .. n-1 of the only system.
+    auto enqueue_step = [&](int64_t tiles, int64_t n_act, bool uniform, int ipsi, int iacc) {
+      const bool q = !uniform;
+      const unsigned grid = (unsigned)tiles;
+      TermArgs<R> ta;
+      std::memset(&ta, 0, sizeof(ta));
+      ta.fields = dF;
+      ta.coef = dCoef;
+      ta.job_field = dJf;
+      ta.part_norm = dPn;
+      ta.tile_job = dTileJob;
+      ta.jobs = dJobs;
+      ta.systab = dSys;
+      ta.nbx = nbx0;
+      ta.tiles = tiles;
+      ta.njobs = (int32_t)n_act;
+      ta.n_terms = nt;
+      ta.remap = remap;
+      ta.acc = bufs[iacc];
+      cx<R> *even = bufs[ipsi], *odd = bufs[iodd];
+      // n = 0: phi_1 = Gh phi_0
+      ta.phin = even;
+      ta.phio = odd;
+      ta.n = 0;
+      ta.dnext = D + slab;
+      ta.dfirst = D;
+      log.mark(st);
+      launch_term<R>(kFirst, kind, stream_nt, q, grid, st, ta, sa0);
+      double bytes = 28.0 * eb;
+      for (int n = 1; n + 1 < nt; ++n) {
+        // phi_{n+1} = 2 Gh phi_n - phi_{n-1}, written over phi_{n-1}; every third launch also
+        // adds phi_{n-1}, phi_n, phi_{n+1} to the step accumulator.
+        ta.phin = (n & 1) ? odd : even;
+        ta.phio = (n & 1) ? even : odd;
+        ta.n = n;
+        ta.dnext = D + (int64_t)(n + 1) * slab;
+        const bool acc3 = (n % 3) == 0;
+        launch_term<R>(acc3 ? kAcc3 : kPlain, kind, stream_nt, q, grid, st, ta, sa0);
+        bytes += (acc3 ? 42.0 : 26.0) * eb;
+      }
+      log.mark(st);
+      log.close(0);
+      if (log.on) {
+        double el = 0.0;   // wavepacket elements of the launch
+        for (int32_t s : active) el += 4.0 * (double)hJobs[s].Z;
+        g_prof.term_launches += nt - 1;
+        g_prof.elems += (double)(nt - 1) * el;
+        g_prof.bytes += bytes * el;
+        g_prof.quad_launches += 1;
+        g_prof.terms = nt;
+      }
+      QuadArgs<R> qa;
+      std::memset(&qa, 0, sizeof(qa));
+      qa.d = D;
+      qa.slab = slab;
+      qa.ell = dEll;
+      qa.job_field = dJf;
+      qa.part = dPq;
+      qa.tile_job = dTileJob;
+      qa.jobs = dJobs;
+      qa.Z = Z0;
+      qa.nbx = nbx0;
+      qa.tiles = tiles;
+      qa.njobs = (int32_t)n_act;
+      qa.n_terms = nt;
+      qa.rank_pad = rkp;
+      qa.remap = remap;
+      log.mark(st);
+      launch_quad<R>(rcw, q, grid, st, qa);
+      log.mark(st);
+      log.close(1);
+      FinArgs fa;
+      std::memset(&fa, 0, sizeof(fa));
+      fa.part_q = dPq;
+      fa.part_norm = dPn;
+      fa.phi = dPhi;
+      fa.prev_norm = dPrev;
+      fa.flag = flag;
+      fa.job_field = dJf;
+      fa.dt = dDt;
+      fa.stepc = dStep;
+      fa.jobs = q ? dJobs : nullptr;
+      fa.slots = q ? dActive : nullptr;
+      fa.sys_k = dK;
+      fa.nbx = nbx0;
+      fa.njobs = (int32_t)n_act;
+      fa.kS = sys[0].spec.kS;
+      fa.kmin = std::min(sys[0].spec.kS, sys[0].spec.kT);
+      fa.rtol = rtol;
+      fa.ps_t = ps_out;
+      fa.dst = dDst;
+      fa.ps_len = op.ps_len;
+      hipLaunchKernelGGL(k_finalize, dim3((unsigned)n_act), dim3(kBlock), 0, st, fa);
+    };
+    // One captured graph per (tiles, occupied slots, form, buffer parity), replayed while the
+    // occupied set keeps its shape; the slot tables it reads are updated between steps.
+    using GraphKey = std::tuple<int64_t, int64_t, int, int>;
+    std::map<GraphKey, hipGraphExec_t> graphs;
+    // HIP does not promise that destroying an executable graph waits for its launches, so the
+    // call's launches are waited for before its graphs are destroyed.
+    struct GraphsGuard {
+      std::map<GraphKey, hipGraphExec_t> &g;
+      hipStream_t s;
+      ~GraphsGuard() {
+        if (g.empty()) return;
+        (void)hipStreamSynchronize(s);
+        for (auto &kv : g) (void)hipGraphExecDestroy(kv.second);
+      }
+    } graphs_guard{graphs, st};
+    while (!active.empty()) {
+      const int64_t tiles = (int64_t)hTile.size(), n_act = (int64_t)active.size();
+      const bool uniform = one_system && active.back() == n_act - 1;
+      if (use_graph) {
+        const GraphKey key{tiles, n_act, uniform ? 1 : 0, ip};
+        auto it = graphs.find(key);
+        if (it == graphs.end()) {
+          HIPCHK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+          enqueue_step(tiles, n_act, uniform, ip, ia_);
+          hipGraph_t g = nullptr;
+          const hipError_t ec = hipStreamEndCapture(st, &g);
+          if (ec != hipSuccess || !g) return fail(RP_EDEVICE, std::string("graph capture: ") + hipGetErrorString(ec));
+          hipGraphExec_t ge = nullptr;
+          const hipError_t ei = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
+          (void)hipGraphDestroy(g);
+          if (ei != hipSuccess) return fail(RP_EDEVICE, std::string("graph instantiate: ") + hipGetErrorString(ei));
+          it = graphs.emplace(key, ge).first;
+        }
+        HIPCHK(hipGraphLaunch(it->second, st));
+      } else {
+        enqueue_step(tiles, n_act, uniform, ip, ia_);
         HIPCHK(hipGetLastError());
       }
-      hipLaunchKernelGGL(k_fill, dim3(grid1(nj)), dim3(256), 0, st, dPhi, nj, 0.0);
-      hipLaunchKernelGGL(k_fill, dim3(grid1(nj)), dim3(256), 0, st, dPrev, nj, 1.0 + 1e-6);
-      hipLaunchKernelGGL(k_fill_i32, dim3(grid1(nj)), dim3(256), 0, st, dStep, nj, 0);
+      std::swap(ip, ia_);
+      // Jobs that have done their steps: yields out, next jobs in.
+      done.clear();
+      for (int32_t s : active)
+        if (--slot_left[s] == 0) done.push_back(s);
+      if (done.empty()) continue;
+      HIPCHK(hipMemcpyAsync(dDone, done.data(), done.size() * 4, hipMemcpyHostToDevice, st));
+      hipLaunchKernelGGL(k_slots_scatter, dim3(grid1((int64_t)done.size())), dim3(256), 0, st, (const int32_t *)dDone,
+                         (int64_t)done.size(), (const double *)dPhi, (const int64_t *)dDst, phi_out);
       HIPCHK(hipGetLastError());
-      int ip = 0, ia_ = 2, iodd = 1;   // psi, accumulator and odd-term buffers
-      const int64_t slab = ch.sZ;
-      // All launches of one step: Chebyshev terms, in-step quadrature, finalisation.
-      auto enqueue_step = [&](int64_t active, int ipsi, int iacc) {
-        const int64_t tiles = tile_start[active];
-        const unsigned grid = (unsigned)tiles;
-        TermArgs<R> ta;
-        std::memset(&ta, 0, sizeof(ta));
-        ta.fields = dF;
-        ta.coef = dCoef;
-        ta.job_field = dJf;
-        ta.part_norm = dPn;
-        ta.tile_job = dTileJob;
-        ta.jobs = dJobs;
-        ta.systab = dSys;
-        ta.nbx = nbx0;
-        ta.tiles = tiles;
-        ta.njobs = (int32_t)active;
-        ta.n_terms = nt;
-        ta.remap = remap;
-        ta.acc = bufs[iacc];
-        cx<R> *even = bufs[ipsi], *odd = bufs[iodd];
-        // n = 0: phi_1 = Gh phi_0
-        ta.phin = even;
-        ta.phio = odd;
-        ta.n = 0;
-        ta.dnext = D + slab;
-        ta.dfirst = D;
-        const double eb = (double)sizeof(R) / 4.0;   // bytes per element, in units of complex-FP32 bytes
-        log.mark(st);
-        launch_term<R>(kFirst, kind, stream_nt, ch.queue, grid, st, ta, sa0);
-        double bytes = 28.0 * eb;
-        for (int n = 1; n + 1 < nt; ++n) {
-          // phi_{n+1} = 2 Gh phi_n - phi_{n-1}, written over phi_{n-1}; every third launch also
-          // adds phi_{n-1}, phi_n, phi_{n+1} to the step accumulator.
-          ta.phin = (n & 1) ? odd : even;
-          ta.phio = (n & 1) ? even : odd;
-          ta.n = n;
-          ta.dnext = D + (int64_t)(n + 1) * slab;
-          const bool acc3 = (n % 3) == 0;
-          launch_term<R>(acc3 ? kAcc3 : kPlain, kind, stream_nt, ch.queue, grid, st, ta, sa0);
-          bytes += (acc3 ? 42.0 : 26.0) * eb;
-        }
-        log.mark(st);
-        log.close(0);
-        if (log.on) {
-          int64_t el = 0;   // wavepacket elements of the launch
-          for (int64_t q = 0; q < active; ++q) el += 4 * hJobs[q].Z;
-          g_prof.term_launches += nt - 1;
-          g_prof.elems += (double)(nt - 1) * (double)el;
-          g_prof.bytes += bytes * (double)el;
-          g_prof.quad_launches += 1;
-          g_prof.terms = nt;
-        }
-        QuadArgs<R> qa;
-        std::memset(&qa, 0, sizeof(qa));
-        qa.d = D;
-        qa.slab = slab;
-        qa.ell = dEll;
-        qa.job_field = dJf;
-        qa.part = dPq;
-        qa.tile_job = dTileJob;
-        qa.jobs = dJobs;
-        qa.Z = sp0.Z;
-        qa.nbx = nbx0;
-        qa.tiles = tiles;
-        qa.njobs = (int32_t)active;
-        qa.n_terms = nt;
-        qa.rank_pad = rkp;
-        qa.remap = remap;
-        log.mark(st);
-        launch_quad<R>(rcw, ch.queue, grid, st, qa);
-        log.mark(st);
-        log.close(1);
-        FinArgs fa;
-        std::memset(&fa, 0, sizeof(fa));
-        fa.part_q = dPq;
-        fa.part_norm = dPn;
-        fa.phi = dPhi;
-        fa.prev_norm = dPrev;
-        fa.flag = flag;
-        fa.job_field = dJf;
-        fa.dt = dDt;
-        fa.stepc = dStep;
-        fa.jobs = ch.queue ? dJobs : nullptr;
-        fa.sys_k = dK;
-        fa.nbx = nbx0;
-        fa.njobs = (int32_t)active;
-        fa.kS = sp0.kS;
-        fa.kmin = std::min(sp0.kS, sp0.kT);
-        fa.rtol = rtol;
-        fa.ps_t = ps_out;
-        fa.dst = dDst;
-        fa.ps_len = op.ps_len;
-        hipLaunchKernelGGL(k_finalize, dim3((unsigned)active), dim3(kBlock), 0, st, fa);
-      };
-      // One captured graph per (active jobs, buffer parity) of this chunk, replayed every step.
-      using GraphKey = std::pair<int64_t, int>;
-      std::map<GraphKey, hipGraphExec_t> graphs;
-      // HIP does not promise that destroying an executable graph waits for its launches, so the
-      // chunk's launches are waited for before its graphs are destroyed.
-      struct GraphsGuard {
-        std::map<GraphKey, hipGraphExec_t> &g;
-        hipStream_t s;
-        ~GraphsGuard() {
-          if (g.empty()) return;
-          (void)hipStreamSynchronize(s);
-          for (auto &kv : g) (void)hipGraphExecDestroy(kv.second);
-        }
-      } graphs_guard{graphs, st};
-      const int64_t steps_max = nsteps[jobs[ch.j0].field];
-      int64_t active = nj;
-      for (int64_t t = 0; t < steps_max; ++t) {
-        // Jobs with more than t steps form a prefix of the chunk.
-        while (active > 0 && nsteps[jobs[ch.j0 + active - 1].field] <= t) --active;
-        if (active <= 0) break;
-        if (use_graph) {
-          const GraphKey key{active, ip};
-          auto it = graphs.find(key);
-          if (it == graphs.end()) {
-            HIPCHK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
-            enqueue_step(active, ip, ia_);
-            hipGraph_t g = nullptr;
-            const hipError_t ec = hipStreamEndCapture(st, &g);
-            if (ec != hipSuccess || !g) return fail(RP_EDEVICE, std::string("graph capture: ") + hipGetErrorString(ec));
-            hipGraphExec_t ge = nullptr;
-            const hipError_t ei = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
-            (void)hipGraphDestroy(g);
-            if (ei != hipSuccess) return fail(RP_EDEVICE, std::string("graph instantiate: ") + hipGetErrorString(ei));
-            it = graphs.emplace(key, ge).first;
-          }
-          HIPCHK(hipGraphLaunch(it->second, st));
-        } else {
-          enqueue_step(active, ip, ia_);
-          HIPCHK(hipGetLastError());
-        }
-        std::swap(ip, ia_);
+      bool emptied = false;
+      for (int32_t s : done) {
+        if (assign(s)) fresh.push_back(s);
+        else emptied = true;
       }
-      hipLaunchKernelGGL(k_scatter, dim3(grid1(nj)), dim3(256), 0, st, (const double *)dPhi, (const int64_t *)dDst,
-                         phi_out, nj);
-      HIPCHK(hipGetLastError());
+      if ((rc = start(ip))) return rc;
+      if (emptied && (rc = relayout())) return rc;
     }
     return RP_OK;
   }

@@ -41,7 +41,7 @@ _lib = None
 EXPORTS = ["rp_sample", "rp_propagate", "rp_yield", "rp_strerror", "rp_last_error", "rp_bessel_j",
            "rp_plan_field", "rp_profile_last", "rp_mlp_param_count", "rp_mlp_workspace_floats",
            "rp_mlp_features", "rp_mlp_forward", "rp_mlp_train_step", "rp_cv_beta", "rp_combine",
-           "rp_design_size", "rp_group_mean", "rp_propagate_static"]
+           "rp_design_size", "rp_group_mean", "rp_propagate_static", "rp_probe_stream"]
 RP_FLAG_PROFILE = 1
 RP_FLAG_TILED = 2
 RP_FLAG_XCD_LOCAL = 4
@@ -86,6 +86,8 @@ def lib():
         L.rp_bessel_j.argtypes = [ctypes.c_double, i32, dp]
         L.rp_plan_field.argtypes = [sp, ctypes.c_double, op, dp, dp, dp]
         L.rp_profile_last.argtypes = [dp, i32]
+        L.rp_probe_stream.argtypes = [i32, vp, vp, vp, i64, i32, dp, vp]
+        L.rp_probe_stream.restype = ctypes.c_int
         for f in ("rp_sample", "rp_propagate", "rp_propagate_static", "rp_yield", "rp_bessel_j", "rp_plan_field", "rp_profile_last",
                   "rp_mlp_features", "rp_mlp_forward", "rp_mlp_train_step", "rp_cv_beta", "rp_combine",
                   "rp_group_mean"):
@@ -301,6 +303,22 @@ def mlp_train_step(params, adam_m, adam_v, step, x, target, n_in, width=256, dep
                                    _dev_ptr(x, torch.float32), _dev_ptr(target, torch.float32), rows,
                                    float(lr), _dev_ptr(grad_out, torch.float32), _dev_ptr(sq_err, torch.float32),
                                    _dev_ptr(ws, torch.float32), _stream(torch)))
+
+
+def probe_stream(bytes_, reps=10):
+    """rp_probe_stream over fresh CUDA buffers of bytes_ bytes: GB/s of each streaming pattern,
+    counting every byte read and written: {"copy": .., "read2_write1": .., "read": .., "write": ..}."""
+    import torch
+    n = bytes_ // 16 * 16
+    bufs = [torch.ones(n // 4, dtype=torch.float32, device="cuda") for _ in range(3)]
+    out = {}
+    moved = {0: 2, 1: 3, 2: 1, 3: 1}
+    for kind, name in ((0, "copy"), (1, "read2_write1"), (2, "read"), (3, "write")):
+        ms = ctypes.c_double(0.0)
+        _check(lib().rp_probe_stream(kind, _dev_ptr(bufs[0], torch.float32), _dev_ptr(bufs[1], torch.float32),
+                                     _dev_ptr(bufs[2], torch.float32), n, reps, ctypes.byref(ms), _stream(torch)))
+        out[name] = moved[kind] * n / (ms.value * 1e-3) / 1e9
+    return out
 
 
 def profile_last():
