@@ -204,8 +204,9 @@ def cv_headline(args):
 
 def sequential_sweep(nB, eps, initial, draw, stats, say, label):
     """The stopping rule every estimator of the headline shares: each round draws fresh units
-    (samples, or design groups) for the fields whose standard error is still above eps, as many
-    as n (err / eps_f)^2 x 1.05 from the current error (at least one more), until none is.
+    (samples, or design groups) for each field whose standard error is still above eps, as many
+    as that field needs, n (err / eps_f)^2 x 1.05 from its current error (at least one more),
+    until none is; fields that need the same number share one draw.
     draw(fields, n, first) -> CUDA [len(fields)][n] new units; stats(f, units) -> (mean, err,
     ratio): the estimate, its error, and the ratio of the units' own error to the error they
     must reach (err / eps, or a smaller target when another estimate is combined in).  Returns
@@ -220,11 +221,13 @@ def sequential_sweep(nB, eps, initial, draw, stats, say, label):
         todo = np.nonzero(need > done)[0]
         if todo.size == 0:
             break
-        n = int(np.max(need[todo] - done[todo]))
-        first = int(done[todo].max())
-        new = draw(todo, n, first)
-        for j, f in enumerate(todo):
-            store[f] = new[j] if store[f] is None else torch.cat([store[f], new[j]])
+        # fields that need the same number of new units share one draw (and one call)
+        for n in sorted(set(int(x) for x in need[todo] - done[todo])):
+            fields = todo[need[todo] - done[todo] == n]
+            new = draw(fields, n, int(done[fields].max()))
+            for j, f in enumerate(fields):
+                store[f] = new[j] if store[f] is None else torch.cat([store[f], new[j]])
+        for f in todo:
             done[f] = store[f].numel()
             m, e, ratio = stats(f, store[f])
             mean[f], err[f] = m, e
@@ -672,12 +675,147 @@ def histogram(args):
                       "dtype": f"f{args.precision}", "wall_s": time.perf_counter() - t0, "fields": out}), flush=True)
 
 
+def batched_classes(args):
+    """The batched workload (256 uneven systems) by size class, on a horizon cut to args.class_t
+    us (the cost of a propagation is linear in its horizon; the full workload is about 6.6 h at
+    70 % of the HBM peak): for every N = 8..18 the first args.per_class systems of that size,
+    every eighth of their 32 fields and args.samples_per_step samples, one call per class; then
+    all of them in one call (the LDS-resident launches plus one job queue of unequal Z).  Rates
+    are in wavepacket-microseconds per second and, divided by each system's own horizon, in
+    propagations per second at the workload's horizons; the tiled classes also report the term
+    kernel's algorithmic GB/s from a profiled call."""
+    import dataclasses
+    import torch
+    from paper_1612_09517_amd import rp, workloads
+    torch.cuda.set_device(0)
+    w = workloads.batched_c3()
+    M = args.samples_per_step
+    fsel = list(range(0, w.fields_mT.shape[1], 8))
+    chosen, classes = [], []
+    for N in range(8, 19):
+        idx = [i for i, x in enumerate(w.systems) if x.N == N][:args.per_class]
+        chosen += idx
+        classes.append((N, idx))
+    t00 = time.perf_counter()
+
+    def run(idx, profile=False):
+        full = [w.systems[i] for i in idx]
+        systems = [dataclasses.replace(x, T_us=min(x.T_us, args.class_t)) for x in full]
+        B = w.fields_mT[idx][:, fsel]
+        cat = torch.cat([rp.sample(x, w.seed, M).reshape(-1) for x in systems])
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rp.propagate(systems, B, cat, M, precision=args.precision)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        jobs = len(idx) * B.shape[1] * M
+        wp_us = sum(x.T_us for x in systems) * B.shape[1] * M
+        full_props = sum(x.T_us / y.T_us for x, y in zip(systems, full)) * B.shape[1] * M
+        out = {"systems": len(idx), "jobs": jobs, "horizon_us": [round(x.T_us, 3) for x in systems], "wall_s": dt,
+               "wavepacket_us_per_s": wp_us / dt, "propagations_per_s_at_own_horizon": full_props / dt}
+        if profile:
+            rp.propagate(systems, B, cat, M, precision=args.precision, profile=True)
+            p = rp.profile_last()
+            gbs = p["elements"] * p["bytes_per_element"] / (p["term_ms"] * 1e-3) / 1e9
+            out.update({"term_GBps": gbs, "term_frac_of_8TBps": gbs / PEAK_HBM_GBS,
+                        "term_time_frac": p["term_ms"] / p["total_ms"], "quad_time_frac": p["quad_ms"] / p["total_ms"]})
+        return out
+
+    rec = {"metric": "batched workload by size class", "dtype": f"f{args.precision}", "samples": M,
+           "fields": [float(x) for x in w.fields_mT[0][fsel]], "per_class": args.per_class,
+           "horizon_cut_us": args.class_t, "classes": {}}
+    for N, idx in classes:
+        rec["classes"][f"N={N} Z={2 ** N}"] = run(idx, profile=2 ** N > (1024 if args.precision == 32 else 512))
+        print(json.dumps({"progress": f"class N={N} done", "t_s": round(time.perf_counter() - t00, 1)}),
+              file=sys.stderr, flush=True)
+    rec["all_in_one_call"] = run(chosen)
+    print(json.dumps(rec), flush=True)
+
+
+def mlp_timing(args):
+    """The control-variate network's kernels on their own: one Adam training step (forward,
+    backward, update) and one forward pass of the 43 -> 3 x 256 -> 1 network on a batch of 512
+    rows, averaged over 200 calls, with the MFMA work they do."""
+    import torch
+    from paper_1612_09517_amd import rp
+    torch.cuda.set_device(0)
+    n_in, width, depth, rows = 43, 256, 3, 512
+    rng = np.random.default_rng(0)
+    P = torch.tensor(rng.normal(0, 0.05, rp.mlp_param_count(n_in, width, depth)).astype(np.float32), device="cuda")
+    Mo, V = torch.zeros_like(P), torch.zeros_like(P)
+    x = rp.mlp_features(torch.tensor(rng.uniform(-1, 1, (rows, 14, 2)), device="cuda"), [1.0], n_in)
+    t = torch.tensor(rng.normal(0, 1, rows).astype(np.float32), device="cuda")
+    ws = rp.mlp_workspace(n_in, width, depth, rows)
+    pad = rp.mlp_in_pad(n_in)
+    flops_fwd = 2 * rows * (pad * width + (depth - 1) * width * width)
+    out = {}
+    for name, fn, fl in (("train_step", lambda i: rp.mlp_train_step(P, Mo, V, i + 1, x, t, n_in, width, depth, lr=1e-4,
+                                                                     workspace=ws), 3 * flops_fwd),
+                         ("forward", lambda i: rp.mlp_forward(P, x, n_in, width, depth, workspace=ws), flops_fwd)):
+        for i in range(10):
+            fn(i)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i in range(200):
+            fn(i)
+        torch.cuda.synchronize()
+        us = (time.perf_counter() - t0) / 200 * 1e6
+        out[name] = {"us_per_call": us, "gemm_TFLOPs": fl / (us * 1e-6) / 1e12}
+    print(json.dumps({"metric": "control-variate network kernels", "rows": rows, "net": f"{n_in}->{depth}x{width}->1",
+                      **out}), flush=True)
+
+
+def convergence(args):
+    """The Sec. IV model's field sweep at M = 100, 200 and 400 (the convergence study of Fig. 2:
+    M = 100 and M = 200 against a well converged M = 400), from three disjoint sets of seeded
+    samples (0..99, 100..299, 300..699).  One call computes the samples args.sample_range a:b
+    for every field (complex FP32) and saves the yields [fields][b - a] to args.out (.npy);
+    with args.combine it reads the saved files and prints the three curves with their errors
+    (Eq. 23) and the deviations of M = 100 and 200 from M = 400."""
+    from paper_1612_09517_amd import workloads
+    w = workloads.paper_model(n_fields=args.fields)
+    s = w.systems[0]
+    B = w.fields_mT
+    if args.combine:
+        parts = [np.load(f) for f in args.combine.split(",")]
+        phi = np.concatenate(parts, axis=1)
+        sets = {"M100": phi[:, :100], "M200": phi[:, 100:300], "M400": phi[:, 300:700]}
+        out = {}
+        for k, v in sets.items():
+            out[k] = {"mean": v.mean(axis=1).tolist(), "eps": (v.std(axis=1, ddof=1) / np.sqrt(v.shape[1])).tolist()}
+        ref = np.array(out["M400"]["mean"])
+        for k in ("M100", "M200"):
+            d = np.array(out[k]["mean"]) - ref
+            e = np.hypot(np.array(out[k]["eps"]), np.array(out["M400"]["eps"]))
+            out[k]["max_abs_dev_from_M400"] = float(np.abs(d).max())
+            out[k]["max_dev_over_err"] = float(np.max(np.abs(d) / e))
+        print(json.dumps({"metric": "Fig. 2 convergence study, Sec. IV model", "fields_mT": B[0].tolist(), **out}),
+              flush=True)
+        return
+    import torch
+    from paper_1612_09517_amd import rp
+    torch.cuda.set_device(0)
+    a, b = (int(x) for x in args.sample_range.split(":"))
+    t0 = time.perf_counter()
+    parts = []
+    for m0 in range(a, b, args.samples_per_step):
+        m = min(args.samples_per_step, b - m0)
+        ang = rp.sample(s, w.seed, m, first=m0)
+        parts.append(rp.propagate(s, B, ang, m, precision=args.precision)[0].cpu().numpy())
+        print(json.dumps({"progress": f"samples {m0 + m - a}/{b - a}", "t_s": round(time.perf_counter() - t0, 1)}),
+              flush=True)
+    phi = np.concatenate(parts, axis=1)
+    np.save(args.out, phi)
+    print(json.dumps({"saved": args.out, "shape": list(phi.shape), "wall_s": time.perf_counter() - t0,
+                      "propagations_per_s": phi.size / (time.perf_counter() - t0)}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--samples-per-step", type=int, default=2)
+    ap.add_argument("--samples-per-step", type=int, default=4)
     ap.add_argument("--profile-steps", type=int, default=2,
                     help="extra steps with HIP events around the term launches (roofline)")
     ap.add_argument("--no-headline", action="store_true",
@@ -687,8 +825,9 @@ def main():
     ap.add_argument("--fields", type=int, default=64)
     ap.add_argument("--precision", type=int, default=32, choices=[32, 64])
     ap.add_argument("--rdt", type=float, default=0.0)
-    ap.add_argument("--autotune", action="store_true",
-                    help="pick r*dt and the XCD workgroup order by timed probes (cached) before timing")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="skip the autotuner (r*dt, XCD order, tile kernel, path, axis order by timed probes) "
+                         "and time the library defaults")
     ap.add_argument("--workspace-gb", type=float, default=0.0,
                     help="device workspace cap per call (bounds how many wavepackets run together)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -696,7 +835,7 @@ def main():
                     help="only run the streaming probes over buffers of this many GiB (ceilings; calibrates counters)")
     ap.add_argument("--workload", default="sweep",
                     choices=["sweep", "tiny", "batched", "large", "paper", "trace", "sampling", "arnoldi",
-                             "histogram"])
+                             "histogram", "convergence", "batched-classes", "mlp"])
     ap.add_argument("--trace-n", type=int, default=10, help="trace workload: nuclei of the batched system used")
     ap.add_argument("--field-group", type=int, default=0,
                     help="large/paper workloads: fields per call, with a progress line after each (0: all)")
@@ -704,6 +843,8 @@ def main():
                     help="large/paper workloads: skip the extra profiled call")
     ap.add_argument("--stride", type=int, default=8, help="batched workload: take every stride-th system")
     ap.add_argument("--max-n", type=int, default=12, help="batched workload: only systems with at most this many nuclei")
+    ap.add_argument("--per-class", type=int, default=2, help="batched-classes workload: systems per size class")
+    ap.add_argument("--class-t", type=float, default=1.0, help="batched-classes workload: horizon cut (us)")
     ap.add_argument("--cv", action="store_true",
                     help="headline comparison: FP32 + learned control variate vs plain FP64 sweep wall time")
     ap.add_argument("--cv-train", type=int, default=3072, help="training yields (one direction each)")
@@ -724,6 +865,9 @@ def main():
     ap.add_argument("--design-groups", type=int, default=8, help="design groups per field to start with")
     ap.add_argument("--design-workload", default="cv", choices=["cv", "sweep"],
                     help="--design on the control-variate workload (32 fields) or the bench sweep (64 fields)")
+    ap.add_argument("--sample-range", default="0:100", help="convergence workload: samples a:b of this call")
+    ap.add_argument("--out", default="convergence.npy", help="convergence workload: where to save the yields")
+    ap.add_argument("--combine", default="", help="convergence workload: comma-separated saved files to combine")
     ap.add_argument("--summarize", default="",
                     help="print a per-kernel summary of a rocprofv3 CSV directory and exit")
     args = ap.parse_args()
@@ -748,6 +892,15 @@ def main():
         return
     if args.workload == "histogram":
         histogram(args)
+        return
+    if args.workload == "convergence":
+        convergence(args)
+        return
+    if args.workload == "batched-classes":
+        batched_classes(args)
+        return
+    if args.workload == "mlp":
+        mlp_timing(args)
         return
     if args.workload != "sweep":
         other_workload(args)
@@ -780,14 +933,20 @@ def main():
               flush=True)
 
     tuned = {"rdt": args.rdt, "xcd": None}
-    if args.autotune:
+    t_tune = 0.0
+    if not args.no_autotune:
+        import tempfile
         from paper_1612_09517_amd import autotune
-        tuned = autotune.tune(s, B[0], precision=args.precision)
+        t0 = time.perf_counter()
+        with tempfile.TemporaryDirectory() as td:     # probe afresh on this GPU
+            tuned = autotune.tune(s, B[0], precision=args.precision, cache=os.path.join(td, "tune.json"))
+        t_tune = time.perf_counter() - t0
+        say(f"autotuned in {t_tune:.1f} s: {tuned}")
 
     def step(i, profile=False):
         ang = rp.sample(s, w.seed, Mb, first=i * Mb)
-        phi = rp.propagate(s, B, ang, Mb, precision=args.precision, rdt=tuned["rdt"], xcd=tuned["xcd"],
-                           profile=profile, workspace_bytes=int(args.workspace_gb * 2 ** 30))
+        phi = rp.propagate(s, B, ang, Mb, precision=args.precision, profile=profile,
+                           workspace_bytes=int(args.workspace_gb * 2 ** 30), **tuned)
         mean, err = rp.yield_stats(phi[0])
         return phi, mean, err
 
@@ -801,7 +960,7 @@ def main():
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     props = args.steps * Mb * B.shape[1]
-    value = props / elapsed
+    value = props / elapsed if args.steps else 0.0
     say(f"throughput: {value:.1f} propagations/s")
     # Roofline: one more step with HIP events around the term launches (on the call's stream).
     prof = {"term_ms": 0.0, "term_launches": 0.0, "elements": 0.0, "quad_ms": 0.0, "total_ms": 0.0}
@@ -822,7 +981,7 @@ def main():
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": elapsed / args.steps * 1e3,
+        "ms_per_step": elapsed / args.steps * 1e3 if args.steps else None,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -832,14 +991,16 @@ def main():
                                f"{B.shape[1]} fields 0..10 mT x {Mb} samples per step",
                    "Z": s.Z, "dim": s.dim, "fields": int(B.shape[1]), "samples_per_step": Mb,
                    "precision": f"complex-FP{args.precision} state, FP64 coefficients and reductions",
-                   "launch": {"rdt": tuned["rdt"] or 100.0, "xcd": tuned["xcd"] or "default",
-                              "autotuned": bool(args.autotune), "graphs": True}},
+                   "launch": {**{k: v for k, v in tuned.items() if v is not None},
+                              "autotuned": not args.no_autotune, "autotune_s": round(t_tune, 2),
+                              "graphs": True}},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": achieved / PEAK_HBM_GBS,
                      "traffic": measured_traffic(args.precision, int(nterms),
                                                  prof["elements"] / max(prof["term_launches"], 1)),
                      "algorithmic_bytes_per_launch": prof["elements"] * bpe / max(prof["term_launches"], 1),
-                     "kernel": ("k_cheb_pair (Chebyshev term on index pairs" if args.precision == 32 else
+                     "kernel": ("k_cheb_pair (Chebyshev term on index pairs"
+                                if args.precision == 32 and not tuned.get("term_scalar") else
                                 "k_cheb_tile (Chebyshev term") + "; three launch variants)",
                      "avg_launch_us": prof["term_ms"] * 1e3 / max(prof["term_launches"], 1),
                      "bytes_per_element_term": bpe, "terms_per_step": nterms,

@@ -294,6 +294,18 @@ int rp_group_mean(const double *phi, int32_t nB, int64_t M, int64_t group, doubl
  *                        sq_err [rows] (squared errors before the update).  lr = 0 computes
  *                        gradients without updating.
  */
+/*
+ * rp_mlp_standardize    training targets standardised per field: phi (device, doubles) has
+ *                       rows q = s * nB + b (s < n_rows, field b); with the mean and standard
+ *                       deviation (1/n normalisation; 1 where it is 0) of field b over its first
+ *                       n_fit rows, target[q] = (phi[q] - mean_b) / std_b (device floats).
+ * rp_mlp_loss           mean squared error of g(x) against target over `rows` rows, into the
+ *                       device double *mse (the validation loss of early stopping).
+ */
+int rp_mlp_standardize(const double *phi, int32_t nB, int64_t n_rows, int64_t n_fit, float *target,
+                       void *hip_stream);
+int rp_mlp_loss(int32_t n_in, int32_t width, int32_t depth, const float *params, const float *x,
+                const float *target, int64_t rows, double *mse, float *workspace, void *hip_stream);
 int64_t rp_mlp_param_count(int32_t n_in, int32_t width, int32_t depth);
 int64_t rp_mlp_workspace_floats(int32_t n_in, int32_t width, int32_t depth, int64_t rows);
 int rp_mlp_features(const double *angles, int64_t M, int32_t N, const double *B_mT, int32_t nB,
@@ -344,9 +356,10 @@ int rp_cv_beta(const double *phi, const double *g, int32_t nB, int64_t M, double
 
 /*
  * rp_probe_stream -- measurement helper: the practical HBM ceilings the term kernel is quoted
- * against.  Times `reps` launches (after one warm-up) of a plain streaming kernel over
- * `bytes` bytes (a multiple of 16) with 16-byte vector accesses, on hip_stream, and waits for
- * them.  kind 0: c = a (reads and writes `bytes` each); 1: c = a + b (two reads, one write);
+ * against.  Times `reps` launches (after one warm-up) of plain streaming kernels over `bytes`
+ * bytes (a multiple of 16) with 16-byte vector accesses, on hip_stream, and waits for them;
+ * three variants (one or four vectors per thread, plain or non-temporal) are timed and the
+ * fastest counts.  kind 0: c = a (reads and writes `bytes` each); 1: c = a + b (two reads, one write);
  * 2: reads a only; 3: writes c only.  a, b, c: device buffers of `bytes` bytes (b only for
  * kind 1, a not for kind 3).  *ms_per_launch (host) receives the average launch time.
  */

@@ -36,8 +36,8 @@ __device__ __forceinline__ float gelu_grad(float z) {
   return 0.5f * (1.0f + erff(z * 0.70710678118654752f)) + z * 0.39894228040143268f * expf(-0.5f * z * z);
 }
 
-// C[m][n] = sum_k A(m, k) B(k, n) (+ bias[n]), A(m, k) = A[m*sam + k*sak], B(k, n) = B[k*sbk + n*sbn].
-// One wave computes one 16x16 tile of C with the 16x16x16 BF16 MFMA; 4 waves per workgroup.
+// C[m][n] = sum_k A(m, k) B(k, n) (+ bias[n]), A(m, k) = A[m*sam + k*sak], B(k, n) = B[k*sbk + n*sbn],
+// on the 16x16x16 BF16 MFMA.
 // Epilogue: if Z != null store the pre-activation; if H != null store GELU of it; if
 // ACC, C is added to the existing contents (gradient accumulation is not used: plain store).
 struct GemmArgs {
@@ -47,33 +47,61 @@ struct GemmArgs {
   int64_t sam, sak, sbk, sbn, ldc;
 };
 
+// A workgroup (4 waves) computes a 32 x 32 tile of C: wave w the 16 x 16 quarter (w / 2, w % 2).
+// Per step of 32 in K, the workgroup stages the 32 x 32 slices of A and B in LDS once, rounded
+// to BF16 (each element is loaded and converted once and used by the two waves that need it),
+// then every wave runs two 16x16x16 MFMAs from LDS.  Global loads run along the operand's
+// unit-stride dimension (sak or sam for A, sbn or sbk for B), so they are coalesced for the
+// plain and the transposed operands of the forward and backward passes.  The sum over K runs in
+// the same order as one MFMA per 16 values of K.
+constexpr int kGT = 32;            // C tile edge and K step
+constexpr int kGP = kGT + 8;       // LDS row length in BF16 values (padding against bank conflicts)
+
 __global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
-  const int lane = threadIdx.x & 63;
-  const int64_t tiles_n = (g.N + 15) / 16;
-  const int64_t tile = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-  const int64_t tiles = ((g.M + 15) / 16) * tiles_n;
-  if (tile >= tiles) return;   // whole waves exit together; no barriers in this kernel
-  const int64_t tm = tile / tiles_n, tn = tile - tm * tiles_n;
-  const int64_t row = tm * 16 + (lane & 15);   // A fragment row / B fragment column
-  const int64_t col = tn * 16 + (lane & 15);
+  __shared__ short As[kGT][kGP];   // As[m][k]
+  __shared__ short Bs[kGT][kGP];   // Bs[n][k]
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int64_t tiles_n = (g.N + kGT - 1) / kGT;
+  const int64_t tm = blockIdx.x / tiles_n, tn = blockIdx.x - tm * tiles_n;
+  const int64_t m0 = tm * kGT, n0 = tn * kGT;
+  const bool a_k_fast = g.sak == 1, b_n_fast = g.sbn == 1;
+  const int wm = (w >> 1) * 16, wn = (w & 1) * 16;
   const int kq = 4 * (lane >> 4);
   f32x4 acc = {0.f, 0.f, 0.f, 0.f};
-  for (int64_t k0 = 0; k0 < g.K; k0 += 16) {
-    bf16x4 a, b;
+  for (int64_t k0 = 0; k0 < g.K; k0 += kGT) {
+    // 1024 values of each operand slice, four per thread, the unit-stride index fastest
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const int64_t k = k0 + kq + i;
-      const float av = (row < g.M && k < g.K) ? g.A[row * g.sam + k * g.sak] : 0.f;
-      const float bv = (col < g.N && k < g.K) ? g.B[k * g.sbk + col * g.sbn] : 0.f;
-      a[i] = to_bf16(av);
-      b[i] = to_bf16(bv);
+    for (int q = 0; q < 4; ++q) {
+      const int e = q * 256 + t;
+      const int fast = e & (kGT - 1), slow = e >> 5;
+      {
+        const int mm = a_k_fast ? slow : fast, kk = a_k_fast ? fast : slow;
+        const int64_t m = m0 + mm, k = k0 + kk;
+        As[mm][kk] = to_bf16((m < g.M && k < g.K) ? g.A[m * g.sam + k * g.sak] : 0.f);
+      }
+      {
+        const int nn = b_n_fast ? fast : slow, kk = b_n_fast ? slow : fast;
+        const int64_t n = n0 + nn, k = k0 + kk;
+        Bs[nn][kk] = to_bf16((n < g.N && k < g.K) ? g.B[k * g.sbk + n * g.sbn] : 0.f);
+      }
     }
-    acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc, 0, 0, 0);
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < kGT; kk += 16) {
+      bf16x4 a, b;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        a[i] = As[wm + (lane & 15)][kk + kq + i];
+        b[i] = Bs[wn + (lane & 15)][kk + kq + i];
+      }
+      acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc, 0, 0, 0);
+    }
+    __syncthreads();
   }
-  // Result layout: lane l, register i -> row 4*(l/16) + i, column l % 16 of the tile.
+  // Result layout: lane l, register i -> row 4*(l/16) + i, column l % 16 of the wave's tile.
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
-    const int64_t r = tm * 16 + kq + i, c = tn * 16 + (lane & 15);
+    const int64_t r = m0 + wm + kq + i, c = n0 + wn + (lane & 15);
     if (r < g.M && c < g.N) {
       float z = acc[i] + (g.bias ? g.bias[c] : 0.f);
       if (g.Z) g.Z[r * g.ldc + c] = z;
@@ -203,6 +231,53 @@ __global__ __launch_bounds__(256) void k_features(FeatArgs f) {
   f.x[i] = v;
 }
 
+// Per-field standardisation of training targets: rows q = s * nB + b (s < n_rows, field b);
+// mean and standard deviation (1/n normalisation) of field b over its first n_fit rows; every
+// row of the field becomes (phi - mean) / std (std 1 when it is 0).  One workgroup per field.
+struct StdArgs {
+  const double *phi;
+  float *t;
+  int64_t nB, n_rows, n_fit;
+};
+
+__device__ __forceinline__ double wg_sum(double v, double *lds) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) lds[w] = v;
+  __syncthreads();
+  const double t = lds[0] + lds[1] + lds[2] + lds[3];
+  __syncthreads();
+  return t;
+}
+
+__global__ __launch_bounds__(256) void k_standardize(StdArgs a) {
+  __shared__ double lds[4];
+  const int64_t b = blockIdx.x;
+  double s = 0.0;
+  for (int64_t i = threadIdx.x; i < a.n_fit; i += 256) s += a.phi[i * a.nB + b];
+  const double mean = wg_sum(s, lds) / (double)a.n_fit;
+  double q = 0.0;
+  for (int64_t i = threadIdx.x; i < a.n_fit; i += 256) {
+    const double d = a.phi[i * a.nB + b] - mean;
+    q += d * d;
+  }
+  double sd = sqrt(wg_sum(q, lds) / (double)a.n_fit);
+  if (sd == 0.0) sd = 1.0;
+  for (int64_t i = threadIdx.x; i < a.n_rows; i += 256) a.t[i * a.nB + b] = (float)((a.phi[i * a.nB + b] - mean) / sd);
+}
+
+// Mean squared error of y against t over rows, accumulated in FP64 by one workgroup.
+__global__ __launch_bounds__(256) void k_mse(const float *y, const float *t, int64_t rows, double *out) {
+  __shared__ double lds[4];
+  double s = 0.0;
+  for (int64_t i = threadIdx.x; i < rows; i += 256) {
+    const double e = (double)y[i] - (double)t[i];
+    s += e * e;
+  }
+  const double tot = wg_sum(s, lds);
+  if (threadIdx.x == 0) *out = tot / (double)rows;
+}
+
 unsigned blocks(int64_t n) { return (unsigned)((n + 255) / 256); }
 
 struct Layout {
@@ -239,8 +314,8 @@ int64_t ws_floats(const Layout &L, int64_t rows) {
 void gemm(const float *A, int64_t sam, int64_t sak, const float *B, int64_t sbk, int64_t sbn, const float *bias,
           float *Z, float *H, int64_t M, int64_t N, int64_t K, hipStream_t st) {
   GemmArgs g{A, B, bias, Z, H, M, N, K, sam, sak, sbk, sbn, N};
-  const int64_t tiles = ((M + 15) / 16) * ((N + 15) / 16);
-  hipLaunchKernelGGL(k_gemm, dim3((unsigned)((tiles + 3) / 4)), dim3(256), 0, st, g);
+  const int64_t tiles = ((M + kGT - 1) / kGT) * ((N + kGT - 1) / kGT);
+  hipLaunchKernelGGL(k_gemm, dim3((unsigned)tiles), dim3(256), 0, st, g);
 }
 
 // Forward pass; returns pointer to y inside the workspace.
@@ -352,4 +427,25 @@ extern "C" int rp_mlp_train_step(int32_t n_in, int32_t width, int32_t depth, flo
               (float)(1.0 / (1.0 - std::pow(0.9, (double)step))), (float)(1.0 / (1.0 - std::pow(0.999, (double)step)))};
   if (lr > 0.f) hipLaunchKernelGGL(k_adam, dim3(blocks(L.total)), dim3(256), 0, st, ad);
   return hipGetLastError() == hipSuccess ? RP_OK : mlp_fail(RP_EDEVICE, "training launch failed");
+}
+
+extern "C" int rp_mlp_standardize(const double *phi, int32_t nB, int64_t n_rows, int64_t n_fit, float *target,
+                                  void *hip_stream) {
+  if (nB < 1 || n_rows < 1 || n_fit < 1 || n_fit > n_rows) return mlp_fail(RP_EINVAL, "bad standardisation sizes");
+  if (!phi || !target) return mlp_fail(RP_EINVAL, "null pointer");
+  StdArgs a{phi, target, nB, n_rows, n_fit};
+  hipLaunchKernelGGL(k_standardize, dim3((unsigned)nB), dim3(256), 0, (hipStream_t)hip_stream, a);
+  return hipGetLastError() == hipSuccess ? RP_OK : mlp_fail(RP_EDEVICE, "standardisation launch failed");
+}
+
+extern "C" int rp_mlp_loss(int32_t n_in, int32_t width, int32_t depth, const float *params, const float *x,
+                           const float *target, int64_t rows, double *mse, float *workspace, void *hip_stream) {
+  Layout L;
+  if (!layout_of(n_in, width, depth, L)) return mlp_fail(RP_EINVAL, "bad network shape");
+  if (rows < 1) return mlp_fail(RP_EINVAL, "rows < 1");
+  if (!params || !x || !target || !mse || !workspace) return mlp_fail(RP_EINVAL, "null pointer");
+  hipStream_t st = (hipStream_t)hip_stream;
+  float *y = forward(L, params, x, rows, workspace, nullptr, st);
+  hipLaunchKernelGGL(k_mse, dim3(1), dim3(256), 0, st, (const float *)y, target, rows, mse);
+  return hipGetLastError() == hipSuccess ? RP_OK : mlp_fail(RP_EDEVICE, "loss launch failed");
 }

@@ -19,9 +19,10 @@ For one system and its field sweep:
    optionally combined by rp_combine with the plain mean of the training yields, which are
    independent Monte Carlo samples of the same yield (stream 1).
 
-Every numerical step of the method runs in librp kernels; this module moves device buffers
-between calls, standardises the training targets on the host, picks batches and keeps the
-best parameters (early stopping on a host-side scalar).
+Every numerical step of the method runs in librp kernels (target standardisation and the
+validation loss included); this module moves device buffers between calls, picks batches and
+keeps the best parameters (early stopping on the validation loss, one scalar read back per
+epoch).
 """
 import numpy as np
 
@@ -100,16 +101,11 @@ class ControlVariate:
         n_val = max(2, int(round(n_pf * val_frac)))
         n_tr = n_pf - n_val
         rows_tr = n_tr * nB
-        # Targets standardised per field on the host (input preparation); row r has field r % nB.
-        ph = phi.detach().cpu().numpy().reshape(n_pf, nB)
-        mean = ph[:n_tr].mean(axis=0)
-        std = ph[:n_tr].std(axis=0)
-        std[std == 0] = 1.0
-        t = torch.tensor(((ph - mean) / std).reshape(-1).astype(np.float32), device="cuda")
+        # Targets standardised per field over the training rows (row r has field r % nB).
+        t = rp.mlp_standardize(phi, nB, n_pf, n_tr)
         x = rp.mlp_features(angles, self.B, self.n_in, layout=2)
         x_tr, t_tr = x[:rows_tr], t[:rows_tr]
-        x_va = x[rows_tr:]
-        t_va_h = t[rows_tr:].cpu().numpy()
+        x_va, t_va = x[rows_tr:], t[rows_tr:]
         ws = rp.mlp_workspace(self.n_in, self.width, self.depth, max(batch, x_va.shape[0]))
         best, best_p, bad = np.inf, self.params.clone(), 0
         for ep in range(epochs):
@@ -121,8 +117,7 @@ class ControlVariate:
                 self.step += 1
                 rp.mlp_train_step(self.params, self.m, self.v, self.step, x_ep[i:i + batch], t_tr[i:i + batch],
                                   self.n_in, self.width, self.depth, lr=lr, workspace=ws)
-            y = rp.mlp_forward(self.params, x_va, self.n_in, self.width, self.depth, workspace=ws)
-            val = float(np.mean((y.cpu().numpy() - t_va_h) ** 2))
+            val = float(rp.mlp_loss(self.params, x_va, t_va, self.n_in, self.width, self.depth, workspace=ws))
             self.history.append(val)
             if val < best:
                 best, best_p, bad = val, self.params.clone(), 0

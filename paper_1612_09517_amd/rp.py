@@ -41,7 +41,8 @@ _lib = None
 EXPORTS = ["rp_sample", "rp_propagate", "rp_yield", "rp_strerror", "rp_last_error", "rp_bessel_j",
            "rp_plan_field", "rp_profile_last", "rp_mlp_param_count", "rp_mlp_workspace_floats",
            "rp_mlp_features", "rp_mlp_forward", "rp_mlp_train_step", "rp_cv_beta", "rp_combine",
-           "rp_design_size", "rp_group_mean", "rp_propagate_static", "rp_probe_stream"]
+           "rp_design_size", "rp_group_mean", "rp_propagate_static", "rp_probe_stream",
+           "rp_mlp_standardize", "rp_mlp_loss"]
 RP_FLAG_PROFILE = 1
 RP_FLAG_TILED = 2
 RP_FLAG_XCD_LOCAL = 4
@@ -78,6 +79,10 @@ def lib():
         L.rp_design_size.restype = i64
         L.rp_group_mean.argtypes = [vp, i32, i64, i64, vp, vp]
         L.rp_mlp_forward.argtypes = [i32, i32, i32, vp, vp, i64, vp, vp, vp]
+        L.rp_mlp_standardize.argtypes = [vp, i32, i64, i64, vp, vp]
+        L.rp_mlp_standardize.restype = ctypes.c_int
+        L.rp_mlp_loss.argtypes = [i32, i32, i32, vp, vp, vp, i64, vp, vp, vp]
+        L.rp_mlp_loss.restype = ctypes.c_int
         L.rp_mlp_train_step.argtypes = [i32, i32, i32, vp, vp, vp, i64, vp, vp, i64, ctypes.c_float, vp, vp,
                                         vp, vp]
         L.rp_strerror.argtypes = [ctypes.c_int]
@@ -291,6 +296,28 @@ def mlp_forward(params, x, n_in, width=256, depth=3, workspace=None):
     _check(lib().rp_mlp_forward(n_in, width, depth, _dev_ptr(params, torch.float32), _dev_ptr(x, torch.float32),
                                 rows, _dev_ptr(y, torch.float32), _dev_ptr(ws, torch.float32), _stream(torch)))
     return y
+
+
+def mlp_standardize(phi, nB, n_rows, n_fit):
+    """rp_mlp_standardize: float32 CUDA targets [n_rows * nB] from float64 phi (row s*nB + b)."""
+    import torch
+    phi = phi.contiguous()
+    t = torch.empty(n_rows * nB, dtype=torch.float32, device="cuda")
+    _check(lib().rp_mlp_standardize(_dev_ptr(phi, torch.float64), nB, n_rows, n_fit, _dev_ptr(t, torch.float32),
+                                    _stream(torch)))
+    return t
+
+
+def mlp_loss(params, x, target, n_in, width=256, depth=3, workspace=None):
+    """rp_mlp_loss: mean squared error of the network on (x, target), as a CUDA float64 scalar."""
+    import torch
+    rows = x.shape[0]
+    out = torch.empty(1, dtype=torch.float64, device="cuda")
+    ws = workspace if workspace is not None else mlp_workspace(n_in, width, depth, rows)
+    _check(lib().rp_mlp_loss(n_in, width, depth, _dev_ptr(params, torch.float32), _dev_ptr(x, torch.float32),
+                             _dev_ptr(target.contiguous(), torch.float32), rows, _dev_ptr(out, torch.float64),
+                             _dev_ptr(ws, torch.float32), _stream(torch)))
+    return out
 
 
 def mlp_train_step(params, adam_m, adam_v, step, x, target, n_in, width=256, depth=3, lr=1e-3,

@@ -152,6 +152,28 @@ def test_forward_and_gradient_elementwise_with_bf16_operands():
         assert dev.max() < 1e-5, name
 
 
+def test_target_standardisation_and_validation_loss():
+    """rp_mlp_standardize against its definition (per-field mean and 1/n deviation over the
+    first n_fit rows, applied to every row; a constant field divides by 1), and rp_mlp_loss
+    against the mean of squared differences between the device forward pass and the targets."""
+    rng = np.random.default_rng(12)
+    nB, n_rows, n_fit = 5, 23, 17
+    phi = rng.uniform(0.2, 0.8, (n_rows, nB))
+    phi[:, 3] = 0.5                                    # constant field (exact mean, zero deviation)
+    _say("target standardisation")
+    t = rp.mlp_standardize(_t(phi.reshape(-1), torch.float64), nB, n_rows, n_fit).cpu().numpy().reshape(n_rows, nB)
+    mean, sd = phi[:n_fit].mean(axis=0), phi[:n_fit].std(axis=0)
+    sd[sd == 0] = 1.0
+    assert np.max(np.abs(t - (phi - mean) / sd)) < 1e-6
+    n_in, width, depth = 19, 64, 3
+    p = _net(n_in, width, depth, seed=7)
+    x = rng.normal(0, 1, (77, mlp.in_pad(n_in)))
+    tg = rng.normal(0, 1, 77)
+    mse = float(rp.mlp_loss(_t(p), _t(x), _t(tg), n_in, width, depth))
+    y = rp.mlp_forward(_t(p), _t(x), n_in, width, depth).cpu().numpy().astype(float)
+    assert abs(mse - np.mean((y - tg.astype(np.float32)) ** 2)) < 1e-6 * mse
+
+
 def test_training_reduces_loss():
     n_in, width, depth = 7, 64, 2
     rng = np.random.default_rng(8)

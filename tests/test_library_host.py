@@ -203,3 +203,29 @@ def test_autotune_dimensions_follow_the_system():
     assert names(small, 32) == ["xcd", "term_scalar", "tiled"]
     assert names(small, 64) == ["xcd", "tiled"]
     assert names(mixed, 32) == ["xcd", "term_scalar", "axes_high_first"]
+
+
+def test_sequential_stopping_rule_reaches_eps():
+    """The bench's stopping rule (shared by every estimator of the headline) on synthetic units
+    of known spread: every field ends at or below eps, with about (sigma/eps)^2 units (the rule
+    adds 5 % and rounds up), in a few rounds; fields that start below eps get no more units."""
+    import torch
+    import bench
+    rng = np.random.default_rng(3)
+    sig = np.array([0.02, 0.05, 0.0005, 0.03])
+    eps = 1e-3
+
+    def draw(fields, n, first):
+        return torch.tensor(rng.normal(0.5, 1.0, (len(fields), n)) * sig[fields][:, None])
+
+    def stats(f, u):
+        u = u.numpy()
+        e = u.std(ddof=1) / np.sqrt(len(u))
+        return float(u.mean()), float(e), float(e / eps)
+
+    mean, err, done, rounds = bench.sequential_sweep(len(sig), eps, 64, draw, stats, lambda m: None, "test")
+    assert np.all(err <= eps) and rounds <= 4
+    need = (sig / eps) ** 2
+    assert done[2] == 64                                   # already below eps after the first round
+    for f in (0, 1, 3):
+        assert 0.8 * need[f] < done[f] < 1.6 * need[f], (f, done[f], need[f])
