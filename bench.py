@@ -256,8 +256,10 @@ def headline_sweeps(args, say):
     legs = set(args.headline_legs.split(","))
     out = {"workload": f"{w.systems[0].name}: N=14 spin-1/2 (7+7), Z=16384, {nB} fields {B[0]:g}..{B[-1]:g} mT, "
                        f"T={s.T_us:g} us, kS={s.kS:.4f}, kT={s.kT:.4f} /us",
-           "eps": eps, "rule": "rounds of fresh units for the fields whose standard error is above eps, "
-                               "n (err/eps)^2 x 1.05 each, until every field is at or below eps"}
+           "eps": eps, "rule": "a pilot of 64 wavepackets per field (design: 4 groups of 16; control variate: "
+                               "16 evaluation samples after the training yields), then rounds of fresh units for the "
+                               "fields whose standard error is above eps, n (err/eps)^2 x 1.05 each, until every "
+                               "field is at or below eps"}
 
     def propagate_fields(fields, ang, n, prec):
         parts = []
@@ -298,7 +300,9 @@ def headline_sweeps(args, say):
             ang = rp.sample(s, w.seed + 2, G * R, first=first * R, basis_mode=mode)
             return rp.group_mean(propagate_fields(fields, ang, G * R, 32), R)
 
-        m, e, done, rounds = sequential_sweep(nB, eps, 8, draw_design, plain_stats, say, "FP32 design")
+        # the same pilot as plain Monte Carlo: 64 wavepackets per field (4 groups of 16)
+        m, e, done, rounds = sequential_sweep(nB, eps, max(2, 64 // R), draw_design, plain_stats, say,
+                                              "FP32 design")
         sync()
         wall = time.perf_counter() - t0
         means["design_fp32"] = (m, e)
@@ -389,7 +393,8 @@ def other_workload(args):
     angs = [rp.sample(s, w.seed + i, M, basis_mode=args.sampler) for i, s in enumerate(systems)]
     cat = torch.cat([a.reshape(-1) for a in angs])
     for _ in range(args.warmup):
-        rp.propagate(systems, B, cat, M, precision=args.precision)
+        rp.propagate(systems, B, cat, M, precision=args.precision, workspace_bytes=int(args.workspace_gb * 2 ** 30),
+                     xcd=args.xcd)
     torch.cuda.synchronize()
     # Long single-system sweeps run a few fields per call and report each call.
     group = args.field_group if (args.field_group > 0 and len(systems) == 1) else B.shape[1]
@@ -397,7 +402,8 @@ def other_workload(args):
     for _ in range(args.steps):
         parts = []
         for f0 in range(0, B.shape[1], group):
-            parts.append(rp.propagate(systems, B[:, f0:f0 + group], cat, M, precision=args.precision))
+            parts.append(rp.propagate(systems, B[:, f0:f0 + group], cat, M, precision=args.precision,
+                                      workspace_bytes=int(args.workspace_gb * 2 ** 30), xcd=args.xcd))
             if group < B.shape[1]:
                 torch.cuda.synchronize()
                 print(json.dumps({"progress": f"fields {f0 + len(B[0, f0:f0 + group])}/{B.shape[1]}",
@@ -410,7 +416,8 @@ def other_workload(args):
     prof = None
     if name in ("large", "paper") and not args.no_profile_call:
         # one extra profiled call (tiled kernels) for the term-kernel bandwidth
-        rp.propagate(systems, B, cat, M, precision=args.precision, profile=True)
+        rp.propagate(systems, B, cat, M, precision=args.precision, workspace_bytes=int(args.workspace_gb * 2 ** 30),
+                     profile=True, xcd=args.xcd)
         p = rp.profile_last()
         prof = {"term_ms": p["term_ms"], "quad_ms": p["quad_ms"], "total_ms": p["total_ms"],
                 "term_GBps": p["elements"] * p["bytes_per_element"] / (p["term_ms"] * 1e-3) / 1e9,
@@ -679,7 +686,8 @@ def batched_classes(args):
     """The batched workload (256 uneven systems) by size class, on a horizon cut to args.class_t
     us (the cost of a propagation is linear in its horizon; the full workload is about 6.6 h at
     70 % of the HBM peak): for every N = 8..18 the first args.per_class systems of that size,
-    every eighth of their 32 fields and args.samples_per_step samples, one call per class; then
+    every eighth of their 32 fields and enough samples (at least args.samples_per_step) for
+    about 2^21 nuclear states per call, one call per class; then
     all of them in one call (the LDS-resident launches plus one job queue of unequal Z).  Rates
     are in wavepacket-microseconds per second and, divided by each system's own horizon, in
     propagations per second at the workload's horizons; the tiled classes also report the term
@@ -702,26 +710,29 @@ def batched_classes(args):
         full = [w.systems[i] for i in idx]
         systems = [dataclasses.replace(x, T_us=min(x.T_us, args.class_t)) for x in full]
         B = w.fields_mT[idx][:, fsel]
+        # samples so that a class holds about 2^21 nuclear states in all (a full job queue)
+        M = max(args.samples_per_step, -(-(1 << 21) // (sum(x.Z for x in systems) * B.shape[1])))
         cat = torch.cat([rp.sample(x, w.seed, M).reshape(-1) for x in systems])
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        rp.propagate(systems, B, cat, M, precision=args.precision)
+        rp.propagate(systems, B, cat, M, precision=args.precision, xcd=args.xcd)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         jobs = len(idx) * B.shape[1] * M
         wp_us = sum(x.T_us for x in systems) * B.shape[1] * M
         full_props = sum(x.T_us / y.T_us for x, y in zip(systems, full)) * B.shape[1] * M
-        out = {"systems": len(idx), "jobs": jobs, "horizon_us": [round(x.T_us, 3) for x in systems], "wall_s": dt,
+        out = {"systems": len(idx), "samples": M, "jobs": jobs, "horizon_us": [round(x.T_us, 3) for x in systems],
+               "wall_s": dt,
                "wavepacket_us_per_s": wp_us / dt, "propagations_per_s_at_own_horizon": full_props / dt}
         if profile:
-            rp.propagate(systems, B, cat, M, precision=args.precision, profile=True)
+            rp.propagate(systems, B, cat, M, precision=args.precision, profile=True, xcd=args.xcd)
             p = rp.profile_last()
             gbs = p["elements"] * p["bytes_per_element"] / (p["term_ms"] * 1e-3) / 1e9
             out.update({"term_GBps": gbs, "term_frac_of_8TBps": gbs / PEAK_HBM_GBS,
                         "term_time_frac": p["term_ms"] / p["total_ms"], "quad_time_frac": p["quad_ms"] / p["total_ms"]})
         return out
 
-    rec = {"metric": "batched workload by size class", "dtype": f"f{args.precision}", "samples": M,
+    rec = {"metric": "batched workload by size class", "dtype": f"f{args.precision}", "min_samples": args.samples_per_step,
            "fields": [float(x) for x in w.fields_mT[0][fsel]], "per_class": args.per_class,
            "horizon_cut_us": args.class_t, "classes": {}}
     for N, idx in classes:
@@ -845,6 +856,8 @@ def main():
     ap.add_argument("--max-n", type=int, default=12, help="batched workload: only systems with at most this many nuclei")
     ap.add_argument("--per-class", type=int, default=2, help="batched-classes workload: systems per size class")
     ap.add_argument("--class-t", type=float, default=1.0, help="batched-classes workload: horizon cut (us)")
+    ap.add_argument("--xcd", default=None, choices=["local", "spread"],
+                    help="batched-classes and other workloads: force the XCD workgroup order")
     ap.add_argument("--cv", action="store_true",
                     help="headline comparison: FP32 + learned control variate vs plain FP64 sweep wall time")
     ap.add_argument("--cv-train", type=int, default=3072, help="training yields (one direction each)")

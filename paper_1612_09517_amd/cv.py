@@ -73,13 +73,13 @@ class ControlVariate:
         import torch
         nB = self.nB
         ang = rp.sample(self.s, self.seed, n_per_field * nB, stream_id=STREAM_TRAIN)
-        phi = torch.empty(n_per_field * nB, dtype=torch.float64, device="cuda")
-        for b in range(nB):
-            a_b = ang[b::nB].contiguous()
-            phi[b::nB] = rp.propagate(self.s, self.B[None, b:b + 1], a_b, n_per_field,
-                                      precision=self.precision)[0, 0]
-            if progress:
-                progress(b + 1, nB)
+        # One call: the system once per field (each copy with its own field and directions), so
+        # that every training yield shares the job queue's launches.
+        per_field = torch.cat([ang[b::nB].reshape(-1) for b in range(nB)])
+        out = rp.propagate([self.s] * nB, self.B[:, None], per_field, n_per_field, precision=self.precision)
+        phi = out[:, 0, :].t().reshape(-1).contiguous()     # row r = s * nB + b
+        if progress:
+            progress(nB, nB)
         return ang, phi
 
     def g(self, angles):

@@ -204,13 +204,19 @@ def test_control_variate_is_unbiased_and_reduces_variance():
     c = cv.ControlVariate(s, B, seed=77, width=64, depth=3)
     _say("cv: generate")
     a_tr, phi_tr = c.generate_training(512)
+    # training yield r: direction r of stream 1 at field r % nB (one call over the system once
+    # per field), against the oracle
+    d = spin.DenseSystem((3, 3), s.two_I, s.a_mT, kS=s.kS, kT=s.kT)
+    ph, at = phi_tr.cpu().numpy(), a_tr.cpu().numpy()
+    for r in (0, 1, 2, 3, 5, 2046):
+        want = yields.FieldOracle(d, B[r % 4], s.T_us).phi(coherent.initial_wavepacket(d, at[r]))
+        assert abs(ph[r] - want) < 1e-5 * want, (r, ph[r], want)
     _say("cv: train")
     c.train(a_tr, phi_tr, epochs=80, batch=256, lr=2e-3)
     c.fit_mu(32768)
     a_ev, phi_ev = c.generate(256, stream=cv.STREAM_EVAL)
     m_cv, e_cv = (t.cpu().numpy() for t in c.estimate(a_ev, phi_ev))
     m_pl, e_pl = (t.cpu().numpy() for t in rp.yield_stats(phi_ev))
-    d = spin.DenseSystem((3, 3), s.two_I, s.a_mT, kS=s.kS, kT=s.kT)
     exact = np.array([yields.FieldOracle(d, b, s.T_us).trace_yield() for b in B])
     _say("cv", m_cv, e_cv, "plain", m_pl, e_pl, "exact", exact, "val mse", c.val_mse)
     assert np.all(np.abs(m_cv - exact) < 4 * e_cv + 1e-5)
