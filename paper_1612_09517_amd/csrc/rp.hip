@@ -902,6 +902,126 @@ __global__ __launch_bounds__(256) void k_quad(QuadArgs<R> qa) {
   }
 }
 
+// The same quadrature in complex FP32 on the matrix cores.  For the 256 nuclear indices of a
+// tile, W = U ell with U[M][n] = (-i)^n d_n(M) is two real products: the real part of
+// (-i)^n d_n is +x, +y, -x, -y of d_n = x + iy for n = 0, 1, 2, 3 (mod 4), the imaginary part
+// +y, -x, -y, +x.  v_mfma_f32_16x16x4_f32 takes four terms per step, lane 16 g + i holding row
+// i (a nuclear index) of term 4 k + g, so term mod 4 = g is fixed per lane and each lane picks
+// and signs its component once per load.  Eight waves own two blocks of 16 rows each (32
+// indices); a pass covers CB blocks of 16 columns, whose factor columns are staged in LDS with
+// the row stride padded off multiples of 32 floats, so that the four term rows of a step fall
+// in distinct banks.  Each wave loads the amplitudes of the next step while the matrix cores
+// work on the current one; eight waves per workgroup (up to seven per SIMD) hide the rest of
+// the latency.  Only the sum of squares of W is kept, so the layout of the results does not
+// matter.
+using f32x4 = float __attribute__((ext_vector_type(4)));
+constexpr int kQuadThreads = 512;
+constexpr int kQuadWaves = kQuadThreads / 64;
+
+__host__ __device__ constexpr int quad_lds_stride(int cb) { return 16 * cb + ((cb & 1) ? 0 : 16); }
+
+template <int CB, bool Q>
+__global__ __launch_bounds__(kQuadThreads) void k_quad_mx(QuadArgs<float> qa) {
+  extern __shared__ float ls[];    // [4 nk][quad_lds_stride(CB)]
+  __shared__ double red[2][kQuadWaves];
+  constexpr int RC = 16 * CB, S = quad_lds_stride(CB);
+  const int64_t L = qa.remap ? xcd_remap(blockIdx.x, qa.tiles) : (int64_t)blockIdx.x;
+  const TileRef t = tile_ref<Q>(qa, L, qa.Z);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int g = lane >> 4, i = lane & 15;
+  const int fi = __builtin_amdgcn_readfirstlane(t.fi);
+  const float *ell = qa.ell + (int64_t)fi * qa.n_terms * qa.rank_pad;
+  const int nt = qa.n_terms, nk = (nt + 3) / 4;
+  const bool swap = (g & 1) != 0;
+  const float sre = (g & 2) ? -1.f : 1.f;
+  const float sim = (g == 1 || g == 2) ? -1.f : 1.f;
+  // rows M0 and M0 + 16 of the tile; a row beyond the job's Z reads as zero
+  const int64_t M0 = t.bx * kBlock + wave * 32 + i;
+  const bool live[2] = {M0 < t.Z, M0 + 16 < t.Z};
+  const cx<float> *src = qa.d + t.amp + M0;
+  auto load = [&](int k, cx<float> (&v)[2]) {
+    const int n = 4 * k + g;
+    const cx<float> *p = src + (int64_t)n * qa.slab;
+#pragma unroll
+    for (int rb = 0; rb < 2; ++rb)
+      v[rb] = (live[rb] && n < nt) ? ld_nt<true>(p + 16 * rb) : cx<float>{0.f, 0.f};
+  };
+  double acc = 0.0;
+  for (int r0 = 0; r0 < qa.rank_pad; r0 += RC) {
+    cx<float> v[2];
+    load(0, v);
+    __syncthreads();   // the previous pass has finished reading ls
+    for (int e = threadIdx.x; e < 4 * nk * (RC / 4); e += kQuadThreads) {
+      const int n = e / (RC / 4), c = 4 * (e - n * (RC / 4));
+      f32x4 w = {0.f, 0.f, 0.f, 0.f};
+      if (n < nt) w = *reinterpret_cast<const f32x4 *>(ell + (int64_t)n * qa.rank_pad + r0 + c);
+      *reinterpret_cast<f32x4 *>(ls + n * S + c) = w;
+    }
+    __syncthreads();
+    f32x4 cre[2][CB], cim[2][CB];
+#pragma unroll
+    for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+      for (int c = 0; c < CB; ++c) cre[rb][c] = cim[rb][c] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int k = 0; k < nk; ++k) {
+      float b[CB];
+#pragma unroll
+      for (int c = 0; c < CB; ++c) b[c] = ls[(4 * k + g) * S + 16 * c + i];
+#pragma unroll
+      for (int rb = 0; rb < 2; ++rb) {
+        const float are = sre * (swap ? v[rb].y : v[rb].x);
+        const float aim = sim * (swap ? v[rb].x : v[rb].y);
+#pragma unroll
+        for (int c = 0; c < CB; ++c) {
+          cre[rb][c] = __builtin_amdgcn_mfma_f32_16x16x4f32(are, b[c], cre[rb][c], 0, 0, 0);
+          cim[rb][c] = __builtin_amdgcn_mfma_f32_16x16x4f32(aim, b[c], cim[rb][c], 0, 0, 0);
+        }
+      }
+      if (k + 1 < nk) load(k + 1, v);
+    }
+    float part = 0.f;   // squares in FP32 per pass, then accumulated in FP64
+#pragma unroll
+    for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+      for (int c = 0; c < CB; ++c)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) part += cre[rb][c][e] * cre[rb][c][e] + cim[rb][c][e] * cim[rb][c][e];
+    acc += (double)part;
+  }
+  double ps = 0.0;   // |d_0|^2 / 2 of each row, from the lanes of term 0
+  if (g == 0) {
+#pragma unroll
+    for (int rb = 0; rb < 2; ++rb)
+      if (live[rb]) {
+        const cx<float> v0 = src[16 * rb];
+        ps += 0.5 * ((double)v0.x * v0.x + (double)v0.y * v0.y);
+      }
+  }
+  acc = warp_sum(acc);
+  ps = warp_sum(ps);
+  if (lane == 0) {
+    red[0][wave] = acc;
+    red[1][wave] = ps;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double s0 = 0.0, s1 = 0.0;
+    for (int w = 0; w < kQuadWaves; ++w) {
+      s0 += red[0][w];
+      s1 += red[1][w];
+    }
+    qa.part[L * 2] = s0;
+    qa.part[L * 2 + 1] = s1;
+  }
+}
+
+// Dynamic LDS of k_quad_mx for a pass of cb column blocks; 0 when it exceeds the 64 KB a
+// launch gets without a raised limit (the VALU kernel runs instead).
+static int64_t quad_mx_lds(int n_terms, int cb) {
+  const int64_t b = (int64_t)4 * ((n_terms + 3) / 4) * quad_lds_stride(cb) * (int64_t)sizeof(float);
+  return b <= 65536 ? b : 0;
+}
+
 // Term kernel variants: any mix of spins, the 256-index tile, and the tile on index pairs.
 enum TermKernel { kTermGen = 0, kTermTile = 1, kTermPair = 2 };
 
@@ -955,8 +1075,28 @@ static void launch_quad_q(int rcw, unsigned grid, hipStream_t st, const QuadArgs
   }
 }
 
+template <bool Q>
+static void launch_quad_mx(int cb, unsigned grid, size_t lds, hipStream_t st, const QuadArgs<float> &qa) {
+  switch (cb) {
+    case 4: hipLaunchKernelGGL((k_quad_mx<4, Q>), dim3(grid), dim3(kQuadThreads), lds, st, qa); break;
+    case 3: hipLaunchKernelGGL((k_quad_mx<3, Q>), dim3(grid), dim3(kQuadThreads), lds, st, qa); break;
+    case 2: hipLaunchKernelGGL((k_quad_mx<2, Q>), dim3(grid), dim3(kQuadThreads), lds, st, qa); break;
+    default: hipLaunchKernelGGL((k_quad_mx<1, Q>), dim3(grid), dim3(kQuadThreads), lds, st, qa); break;
+  }
+}
+
+// Complex FP32 passes of a multiple of 16 columns run on the matrix cores (unless the
+// staged factor would not fit the LDS); everything else on the vector ALUs.
 template <typename R>
 static void launch_quad(int rcw, bool q, unsigned grid, hipStream_t st, const QuadArgs<R> &qa) {
+  if constexpr (std::is_same<R, float>::value) {
+    const int64_t lds = rcw % 16 == 0 ? quad_mx_lds(qa.n_terms, rcw / 16) : 0;
+    if (lds > 0) {
+      if (q) launch_quad_mx<true>(rcw / 16, grid, (size_t)lds, st, qa);
+      else launch_quad_mx<false>(rcw / 16, grid, (size_t)lds, st, qa);
+      return;
+    }
+  }
   if (q) launch_quad_q<R, true>(rcw, grid, st, qa);
   else launch_quad_q<R, false>(rcw, grid, st, qa);
 }
@@ -1631,12 +1771,13 @@ struct TiledRun {
     // Pad the term count so that (nt - 2) is a multiple of 3: the accumulator is updated
     // by the first launch (terms 0, 1) and then by every third launch (three terms each).
     while ((nt - 2) % 3 != 0) ++nt;
-    // k_quad makes passes of rcw <= 64 (FP32) or 32 (FP64) columns, each reading every singlet
-    // amplitude once: the fewest passes that cover the rank, of equal width (a multiple of 8),
-    // with the rank padded by zero columns to passes * rcw.
+    // The quadrature makes passes of rcw <= 64 (FP32) or 32 (FP64) columns, each reading every
+    // singlet amplitude once: the fewest passes that cover the rank, of equal width (a multiple
+    // of 16 in FP32, of 8 in FP64), with the rank padded by zero columns to passes * rcw.
     const int wmax = sizeof(R) == 4 ? 64 : 32;
     const int passes = (rk + wmax - 1) / wmax;
-    rcw = ((rk + passes - 1) / passes + 7) / 8 * 8;
+    const int align = sizeof(R) == 4 ? 16 : 8;   // FP32: whole column blocks of the MFMA kernel
+    rcw = ((rk + passes - 1) / passes + align - 1) / align * align;
     rkp = passes * rcw;
     const int nG = ns * nB;
     fdev.assign(nG, FieldDev<R>());

@@ -348,7 +348,9 @@ def test_underestimated_spectrum_is_reported(tiled):
 
 def test_resident_batch_of_unequal_systems():
     """Systems of 8, 64, 256 and 1024 nuclear states (spin-1/2 and spin-1 mixes) in one call:
-    the LDS-resident launches agree with the tiled kernels and, for the small ones, the oracle."""
+    the LDS-resident launches agree with the tiled kernels and with the oracle (dense route for
+    the two small systems; sparse augmented-system route, on the first three samples, for the
+    256- and 1024-state ones, which run in the largest resident class: 1024-thread workgroups)."""
     rng = np.random.default_rng(11)
     systems = [SpinSystem(2, 1, [1, 1, 1], [0.8, 0.3, 0.5], kS=1.0, kT=1.0, T_us=4.0),
                SpinSystem(3, 2, [1, 2, 1, 2, 1], list(rng.uniform(-0.8, 0.8, 5)), J_mT=0.3, kS=0.4, kT=2.2, T_us=3.0),
@@ -358,6 +360,7 @@ def test_resident_batch_of_unequal_systems():
     M = 5
     angs = [rp.sample(s, 40 + i, M) for i, s in enumerate(systems)]
     cat = torch.cat([a.reshape(-1) for a in angs])
+    oracle_large = {}
     for prec in (32, 64):
         _say("resident batch, precision", prec)
         res = rp.propagate(systems, B, cat, M, precision=prec).cpu().numpy()
@@ -366,6 +369,10 @@ def test_resident_batch_of_unequal_systems():
         for i in (0, 1):
             want = gc.oracle_phi(systems[i], B[i], philox.sample_angles(40 + i, 0, M, systems[i].N))
             assert _rel(res[i], want) < TOL[prec]
+        for i in (2, 3):
+            want = oracle_large[i] if i in oracle_large else oracle_large.setdefault(
+                i, gc.oracle_phi_sparse(systems[i], B[i], philox.sample_angles(40 + i, 0, 3, systems[i].N)))
+            assert _rel(res[i][:, :3], want) < TOL[prec], (i, prec)
 
 
 def test_autotuner_picks_valid_parameters_and_caches(tmp_path):
