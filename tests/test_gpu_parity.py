@@ -127,6 +127,21 @@ def test_general_spins_exchange_triplet_dissipation(prec, tiled):
     assert _rel(phi, want) < TOL[prec]
 
 
+@pytest.mark.parametrize("rdt", [250.0, 400.0])
+@pytest.mark.parametrize("prec", [64, 32])
+def test_long_steps_several_quadrature_passes(prec, rdt):
+    """Long Chebyshev steps: ranks of 86-183 need two to four quadrature passes; in complex FP32
+    the matrix-core kernel runs them at r*dt = 250 (275 terms), and the factor of r*dt = 400
+    (422 terms) no longer fits its LDS, so the vector kernel takes over."""
+    s = SpinSystem(3, 2, [1, 2, 1, 1, 1], [0.8, -0.3, 0.5, 0.6, -0.7], J_mT=0.4, kS=0.5, kT=2.0, T_us=3.0)
+    B = np.array([[0.0, 2.0, 5.0]])
+    _say("long steps, precision", prec, "rdt", rdt)
+    ang = rp.sample(s, 21, 4)
+    phi = rp.propagate(s, B, ang, 4, precision=prec, tiled=True, rdt=rdt).cpu().numpy()[0]
+    want = gc.oracle_phi(s, B[0], philox.sample_angles(21, 0, 4, s.N))
+    assert _rel(phi, want) < TOL[prec]
+
+
 @pytest.mark.parametrize("prec", [64, 32])
 def test_singlet_population_trajectory(prec):
     """ps_t: <psi(t)|P_S|psi(t)> at every step start t_j = j dt of each system and field (dt and
