@@ -94,9 +94,11 @@ typedef struct rp_opts {
    workgroup per wavepacket for the whole propagation, every such job of the call in one
    launch per workgroup size.  Profiled calls always use the tiled kernels. */
 #define RP_FLAG_TILED 2
-/* opts->flags: workgroup order of the tiled kernels.  By default a wavepacket of at most 1 MB
-   goes to one XCD (its partner tiles stay in that XCD's L2) and larger ones are spread over
-   all XCDs; these flags force one or the other (for tuning). */
+/* opts->flags: workgroup order of the tiled kernels.  By default each XCD takes a contiguous
+   eighth of a launch's tiles (whole wavepackets when there are eight or more, so their partner
+   tiles stay in one XCD's L2) while a wavepacket (4Z complex values) is at most 32 MB, and
+   larger ones are spread round-robin over all XCDs; these flags force one or the other (for
+   tuning). */
 #define RP_FLAG_XCD_LOCAL 4
 #define RP_FLAG_XCD_SPREAD 8
 /* opts->flags: launch the tiled kernels directly instead of replaying one captured HIP graph

@@ -109,7 +109,7 @@ def tune(system, fields_mT, precision=32, samples=8, cache=None, force=False, se
     cur = {"rdt": 100.0, "xcd": None}
     for name, values in dimensions(system, precision):
         cur[name] = values[0]
-    cur["xcd"] = "local" if 4 * system.Z * (4 if precision == 32 else 8) * 2 <= (1 << 20) else "spread"
+    cur["xcd"] = "local" if 4 * system.Z * (4 if precision == 32 else 8) * 2 <= (32 << 20) else "spread"
     scores = {rdt: timed({**cur, "rdt": rdt}) for rdt in RDT}
     cur["rdt"] = min(scores, key=scores.get)
     best_v = scores[cur["rdt"]]
