@@ -911,9 +911,9 @@ __global__ __launch_bounds__(256) void k_quad(QuadArgs<R> qa) {
 // indices); a pass covers CB blocks of 16 columns, whose factor columns are staged in LDS with
 // the row stride padded off multiples of 32 floats, so that the four term rows of a step fall
 // in distinct banks.  Each wave loads the amplitudes of the next step while the matrix cores
-// work on the current one; eight waves per workgroup (up to seven per SIMD) hide the rest of
-// the latency.  Only the sum of squares of W is kept, so the layout of the results does not
-// matter.
+// work on the current one; the other waves (seven per SIMD with three column blocks), each
+// starting at its own eighth of the steps, hide the rest of the latency.  Only the sum of
+// squares of W is kept, so the layout of the results does not matter.
 using f32x4 = float __attribute__((ext_vector_type(4)));
 constexpr int kQuadThreads = 512;
 constexpr int kQuadWaves = kQuadThreads / 64;
@@ -946,10 +946,13 @@ __global__ __launch_bounds__(kQuadThreads) void k_quad_mx(QuadArgs<float> qa) {
     for (int rb = 0; rb < 2; ++rb)
       v[rb] = (live[rb] && n < nt) ? ld_nt<true>(p + 16 * rb) : cx<float>{0.f, 0.f};
   };
+  // Wave w starts at step w nk / 8 and wraps around, so that the waves of a workgroup, which
+  // leave the staging barrier together, do not wait for memory in lockstep.
+  const int k0 = wave * nk / kQuadWaves;
   double acc = 0.0;
   for (int r0 = 0; r0 < qa.rank_pad; r0 += RC) {
     cx<float> v[2];
-    load(0, v);
+    load(k0, v);
     __syncthreads();   // the previous pass has finished reading ls
     for (int e = threadIdx.x; e < 4 * nk * (RC / 4); e += kQuadThreads) {
       const int n = e / (RC / 4), c = 4 * (e - n * (RC / 4));
@@ -963,7 +966,8 @@ __global__ __launch_bounds__(kQuadThreads) void k_quad_mx(QuadArgs<float> qa) {
     for (int rb = 0; rb < 2; ++rb)
 #pragma unroll
       for (int c = 0; c < CB; ++c) cre[rb][c] = cim[rb][c] = f32x4{0.f, 0.f, 0.f, 0.f};
-    for (int k = 0; k < nk; ++k) {
+    int k = k0;
+    for (int kk = 0; kk < nk; ++kk) {
       float b[CB];
 #pragma unroll
       for (int c = 0; c < CB; ++c) b[c] = ls[(4 * k + g) * S + 16 * c + i];
@@ -977,7 +981,8 @@ __global__ __launch_bounds__(kQuadThreads) void k_quad_mx(QuadArgs<float> qa) {
           cim[rb][c] = __builtin_amdgcn_mfma_f32_16x16x4f32(aim, b[c], cim[rb][c], 0, 0, 0);
         }
       }
-      if (k + 1 < nk) load(k + 1, v);
+      k = k + 1 == nk ? 0 : k + 1;
+      if (kk + 1 < nk) load(k, v);
     }
     float part = 0.f;   // squares in FP32 per pass, then accumulated in FP64
 #pragma unroll
