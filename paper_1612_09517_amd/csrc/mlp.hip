@@ -160,12 +160,46 @@ struct ColArgs {
   int64_t rows, cols;
 };
 
-__global__ __launch_bounds__(256) void k_colsum(ColArgs c) {
-  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= c.cols) return;
+// Column sums out[j] = sum_r X[r][j] v[r] (v = 1 when null).  A workgroup of 16 waves takes
+// 64 columns: the lanes of a wave are the columns (each row segment one coalesced 256-byte
+// load), wave w the rows w, w + 16, ...; the 16 wave sums are then added in LDS in a fixed
+// order, so the result does not depend on scheduling.
+constexpr int kColWaves = 16;
+__global__ __launch_bounds__(64 * kColWaves) void k_colsum(ColArgs c) {
+  __shared__ float part[kColWaves][64];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int64_t j = (int64_t)blockIdx.x * 64 + lane;
   float s = 0.f;
-  for (int64_t r = 0; r < c.rows; ++r) s += c.X[r * c.cols + j] * (c.v ? c.v[r] : 1.0f);
-  c.out[j] = s;
+  if (j < c.cols)
+    for (int64_t r = w; r < c.rows; r += kColWaves) s += c.X[r * c.cols + j] * (c.v ? c.v[r] : 1.0f);
+  part[w][lane] = s;
+  __syncthreads();
+  if (w == 0 && j < c.cols) {
+    float t = 0.f;
+    for (int k = 0; k < kColWaves; ++k) t += part[k][lane];
+    c.out[j] = t;
+  }
+}
+
+// The sum of one column (cols == 1): threads over rows, then a tree in LDS.
+__global__ __launch_bounds__(1024) void k_sum1(ColArgs c) {
+  __shared__ float part[1024];
+  float s = 0.f;
+  for (int64_t r = threadIdx.x; r < c.rows; r += 1024) s += c.X[r] * (c.v ? c.v[r] : 1.0f);
+  part[threadIdx.x] = s;
+  __syncthreads();
+  for (int h = 512; h > 0; h >>= 1) {
+    if ((int)threadIdx.x < h) part[threadIdx.x] += part[threadIdx.x + h];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) c.out[0] = part[0];
+}
+
+static void colsum(const ColArgs &c, hipStream_t st) {
+  if (c.cols == 1)
+    hipLaunchKernelGGL(k_sum1, dim3(1), dim3(1024), 0, st, c);
+  else
+    hipLaunchKernelGGL(k_colsum, dim3((unsigned)((c.cols + 63) / 64)), dim3(64 * kColWaves), 0, st, c);
 }
 
 // Adam (Kingma & Ba) on the packed FP32 parameters.
@@ -398,9 +432,9 @@ extern "C" int rp_mlp_train_step(int32_t n_in, int32_t width, int32_t depth, flo
   // output layer: dw = H_last^T dy, db = sum dy
   const float *Hl = Hs + R * (L.depth - 1) * W;
   ColArgs c1{Hl, dy, G + L.off_w, R, W};
-  hipLaunchKernelGGL(k_colsum, dim3(blocks(W)), dim3(256), 0, st, c1);
+  colsum(c1, st);
   ColArgs c2{dy, nullptr, G + L.off_bo, R, 1};
-  hipLaunchKernelGGL(k_colsum, dim3(1), dim3(256), 0, st, c2);
+  colsum(c2, st);
   // last hidden layer: dZ = (dy w^T) * gelu'(Z)
   ActArgs a{dy, params + L.off_w, nullptr, Zs + R * (L.depth - 1) * W, dA, R, W};
   hipLaunchKernelGGL(k_act_back, dim3(blocks(R * W)), dim3(256), 0, st, a);
@@ -410,7 +444,7 @@ extern "C" int rp_mlp_train_step(int32_t n_in, int32_t width, int32_t depth, flo
     // dW_l = in^T dZ  (fan x W), K = rows
     gemm(inp, 1, fan, dA, W, 1, nullptr, G + L.off_W[l], nullptr, fan, W, R, st);
     ColArgs cb{dA, nullptr, G + L.off_b[l], R, W};
-    hipLaunchKernelGGL(k_colsum, dim3(blocks(W)), dim3(256), 0, st, cb);
+    colsum(cb, st);
     if (l) {
       // dH_{l-1} = dZ W_l^T  (rows x W), then dZ_{l-1} = dH * gelu'(Z_{l-1})
       gemm(dA, W, 1, params + L.off_W[l], 1, W, nullptr, dB, nullptr, R, W, W, st);
