@@ -1,9 +1,9 @@
 """Launch-parameter autotuner for rp_propagate, with an on-disk cache.
 
 For a system shape it times short probes of the real call -- the same system with a horizon
-shortened to about a dozen Chebyshev steps, three of its fields and as many samples as fill
-the job queue -- and keeps the candidate with the lowest time per simulated microsecond per
-wavepacket.  The candidates are
+shortened to 12 Chebyshev steps of the candidate's own length at the highest field, three of
+its fields and as many samples as fill the job queue -- and keeps the candidate with the lowest
+time per simulated microsecond per wavepacket.  The candidates are
 searched one dimension at a time, starting from the library's defaults:
 
 1. the step length r*dt (RDT);
@@ -29,7 +29,7 @@ import numpy as np
 from . import rp
 
 DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "rpmc", "autotune.json")
-RDT = (60.0, 80.0, 100.0, 120.0, 160.0)
+RDT = (60.0, 80.0, 100.0, 120.0, 130.0, 140.0, 150.0, 160.0)
 XCD = ("local", "spread")
 RESIDENT_MAX = {32: 1024, 64: 512}
 
@@ -39,7 +39,7 @@ def _key(system, precision, r_max):
     gpu = torch.cuda.get_device_name(0) if torch.cuda.is_available() else "cpu"
     spins = (tuple(sorted(system.two_I[:system.n1])), tuple(sorted(system.two_I[system.n1:])))
     return (f"{gpu}|fp{precision}|{spins}|J={system.J_mT != 0}|dk={abs(system.kS - system.kT):.2g}"
-            f"|r~{r_max:.2g}|v3")
+            f"|r~{r_max:.2g}|v4")
 
 
 def _load(path):
@@ -68,14 +68,14 @@ def dimensions(system, precision):
     return dims
 
 
-def tune(system, fields_mT, precision=32, samples=8, cache=None, force=False, seed=12345, repeats=2):
+def tune(system, fields_mT, precision=32, samples=8, cache=None, force=False, seed=12345, repeats=3):
     """Best rp.propagate keyword arguments for `system` over `fields_mT`: 'rdt', 'xcd' and, where
     they apply, 'term_scalar', 'tiled' and 'axes_high_first'.  Probes only on a cache miss.
 
     A probe is sized like production work: at least `samples` samples, and enough wavepackets
     (about 2^21 nuclear states in all, at most 256) to fill the job queue's slots as a sweep
-    does, over a horizon of about 12 of the longest candidate steps, so that step counts round
-    to the same few percent for every r*dt."""
+    does, over a horizon of 12 of the candidate's steps at the highest field, so that rounding
+    the step counts up costs every r*dt the same."""
     import torch
     cache = cache or os.environ.get("RPMC_AUTOTUNE_CACHE", DEFAULT_CACHE)
     B = np.asarray(fields_mT, np.float64).reshape(-1)
@@ -84,15 +84,17 @@ def tune(system, fields_mT, precision=32, samples=8, cache=None, force=False, se
     db = _load(cache)
     if key in db and not force:
         return dict(db[key]["best"])
-    T_probe = min(system.T_us, 12 * max(RDT) / r_max)
-    probe = dataclasses.replace(system, T_us=T_probe)
     Bp = np.unique(np.quantile(B, [0.0, 0.5, 1.0]))[None, :]
     jobs = int(np.clip((1 << 21) // max(system.Z, 1), 8, 256))
     samples = max(samples, -(-jobs // Bp.shape[1]))
-    ang = rp.sample(probe, seed, samples)
+    ang = rp.sample(system, seed, samples)
     results = []
 
     def timed(cand):
+        # Each candidate's horizon is a whole number (12) of its own steps at the highest
+        # field, so that rounding the step count up costs every candidate the same.
+        T_probe = min(system.T_us, 12 * cand["rdt"] / r_max)
+        probe = dataclasses.replace(system, T_us=T_probe)
         kw = dict(precision=precision, **cand)
         rp.propagate(probe, Bp, ang, samples, **kw)
         torch.cuda.synchronize()
