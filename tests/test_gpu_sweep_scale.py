@@ -26,20 +26,24 @@ def _device():
     rp.lib()
 
 
-def _run(prec, B, M):
+def _run(prec, B, M, rdt=0.0):
     w = workloads.sweep_c2()
     s = w.systems[0]
     ang = rp.sample(s, w.seed, M)
-    print("sweep scale: precision", prec, "fields", list(B), "samples", M, flush=True)
-    return rp.propagate(s, np.asarray(B)[None, :], ang, M, precision=prec).cpu().numpy()[0]
+    print("sweep scale: precision", prec, "fields", list(B), "samples", M, "rdt", rdt, flush=True)
+    return rp.propagate(s, np.asarray(B)[None, :], ang, M, precision=prec, rdt=rdt).cpu().numpy()[0]
 
 
-def test_full_size_against_oracle_golden():
+@pytest.mark.parametrize("rdt", [0.0, 150.0])
+def test_full_size_against_oracle_golden(rdt):
+    """At the default step (ranks 45-46 in complex FP32: three 16-column blocks of the
+    matrix-core quadrature) and at r*dt = 150, the step the autotuner picks for this workload
+    (ranks 61-63: four blocks; 80-87 in FP64: three passes of the vector kernel)."""
     g = json.load(open(GOLDEN))
     B = g["fields_mT"]
     M = max(g["samples"]) + 1
     for prec, tol in ((64, 1e-10), (32, 1e-5)):
-        phi = _run(prec, B, M)
+        phi = _run(prec, B, M, rdt)
         for b, Bv in enumerate(B):
             for i in g["samples"]:
                 want = g["phi"][f"{Bv}:{i}"]
