@@ -50,6 +50,12 @@ def _load(path):
         return {}
 
 
+def probe_horizon(system, rdt, r_max, steps=12):
+    """Horizon of a probe for step length `rdt`: `steps` whole steps at the highest field (whose
+    spectral half-width is r_max), or the system's own horizon if that is shorter."""
+    return min(system.T_us, steps * rdt / r_max)
+
+
 def dimensions(system, precision):
     """The categorical dimensions that apply to this system, with their candidate values (the
     library default first)."""
@@ -93,7 +99,7 @@ def tune(system, fields_mT, precision=32, samples=8, cache=None, force=False, se
     def timed(cand):
         # Each candidate's horizon is a whole number (12) of its own steps at the highest
         # field, so that rounding the step count up costs every candidate the same.
-        T_probe = min(system.T_us, 12 * cand["rdt"] / r_max)
+        T_probe = probe_horizon(system, cand["rdt"], r_max)
         probe = dataclasses.replace(system, T_us=T_probe)
         kw = dict(precision=precision, **cand)
         rp.propagate(probe, Bp, ang, samples, **kw)

@@ -3,6 +3,7 @@ Chebyshev/quadrature plan (Bessel coefficients, in-step quadrature factor), the
 latter checked by driving a dense CPU emulation of the propagation with the
 library's own plan and comparing against the oracle."""
 import ctypes
+import dataclasses
 import math
 import os
 import re
@@ -203,6 +204,23 @@ def test_autotune_dimensions_follow_the_system():
     assert names(small, 32) == ["xcd", "term_scalar", "tiled"]
     assert names(small, 64) == ["xcd", "tiled"]
     assert names(mixed, 32) == ["xcd", "term_scalar", "axes_high_first"]
+
+
+def test_autotune_probe_horizon_is_whole_steps():
+    """Every candidate step length is probed over exactly 12 of its own steps at the highest
+    field (as the library's planner counts them), so that rounding the step count up costs every
+    candidate the same; a horizon shorter than that is probed as it is."""
+    from paper_1612_09517_amd import autotune, workloads
+    s = workloads.sweep_c2().systems[0]
+    B = 10.0
+    for prec in (32, 64):
+        r_max = rp.plan_field(s, B, precision=prec)["r"]
+        for rdt in autotune.RDT:
+            T = autotune.probe_horizon(s, rdt, r_max)
+            probe = dataclasses.replace(s, T_us=T)
+            assert rp.plan_field(probe, B, precision=prec, rdt=rdt)["n_steps"] == 12, (prec, rdt)
+    short = dataclasses.replace(s, T_us=0.01)
+    assert autotune.probe_horizon(short, 150.0, 100.0) == 0.01
 
 
 def test_sequential_stopping_rule_reaches_eps():
